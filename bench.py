@@ -1,0 +1,267 @@
+"""Benchmark: forward C2C 3D FFT at 512^3 complex64 on one MI355X.
+
+Prints ONE JSON line.  A step is one forward 3D FFT of the whole grid (the
+three axis passes with their in-LDS transposes) on a PME-style charge grid
+already resident in HBM; `value` is GFLOP/s by the 5 N log2 N convention.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--size 512] [--slabs K]
+                  [--no-cpu-baseline] [--forms] [--calibrate-copy]
+
+The dominant kernel's roofline uses HIP events recorded by the library around
+each pass launch on the stream the pass runs on, over the timed region.
+`--calibrate-copy` instead times a plain device copy of the same bytes (used
+to scale the HBM byte counters); `--forms` adds the half-storage, batched and
+other measured forms to the line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "3D FFT GFLOP/s (5N·log2N) + achieved HBM GB/s at 512³ c64, 1 MI355X"
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = ["paper_2002_04896_amd/csrc/croft_kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_512cube_c64.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def flops_5nlogn(n: int) -> float:
+    return 5.0 * n * math.log2(n) if n > 1 else 0.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--slabs", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(x_c64, n):
+    """Time the FP64 oracle on a bounded sample: 1/8 of the lines of every
+    axis, then extrapolate to the whole transform."""
+    import numpy as np
+    import oracle
+
+    a = x_c64.astype(np.complex128)
+    lines = n * n
+    sample = lines // 8
+    t0 = time.perf_counter()
+    for axis in range(3):
+        oracle.dft_axis_lines(a, axis, 0, sample, -1)
+    dt = time.perf_counter() - t0
+    t_full = dt * (lines / sample)
+    N = n ** 3
+    return {"value": flops_5nlogn(N) / t_full / 1e9, "unit": "GFLOP/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"naive FP64 DFT of {sample} of the {lines} lines of each axis (1/8) of the "
+                      f"{n}^3 PME grid, {dt:.1f} s measured, whole transform extrapolated "
+                      f"({t_full:.1f} s)"}
+
+
+def calibrate_copy(torch, steps, warmup):
+    """A plain device-to-device copy of 1 GiB, for scaling HBM counters."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    nbytes = 2 * src.numel() * 4
+    print(json.dumps({"calibrate_copy_bytes": nbytes, "ms": ms, "GBps": nbytes / ms / 1e6}))
+
+
+def time_plan(torch, croft, plan, fn, steps, warmup, npasses):
+    """Warm up, then time exactly `steps` calls between two synchronisations,
+    with per-pass HIP events recorded by the library."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    croft.croft_plan_profile(plan, True)
+    stream = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    croft.croft_plan_profile(plan, False)
+    pass_ms, n = croft.croft_plan_profile_read(plan, max(npasses, 1))
+    ms = start.elapsed_time(end) / steps
+    return ms, [m / max(n, 1) for m in pass_ms[:npasses]], wall
+
+
+def measure_forms(torch, np, croft, synth, steps):
+    """Half-storage (512^3), batched (64 uneven grids) and inverse forms, each
+    next to the plain FP32 form on the same GPU."""
+    out = {}
+    n = 512
+    N = n ** 3
+    # half storage at 512^3 from N(0,1) inputs quantised on the host
+    v = synth.normal_c((n, n, n), seed=5)
+    for name, dt, kind in (("c16f", croft.CROFT_C16F, "f16"), ("c16b", croft.CROFT_C16B, "bf16")):
+        data, e = synth.quantize_half(v, kind)
+        tdt = torch.float16 if kind == "f16" else torch.bfloat16
+        d_in = torch.from_numpy(data.view(np.int16)).cuda().view(tdt)
+        d_out = torch.empty_like(d_in)
+        e_in = torch.from_numpy(e).cuda()
+        e_out = torch.empty((n, n), dtype=torch.int8, device="cuda")
+        plan = croft.croft_plan_create(n, n, n, dt, croft.CROFT_FORWARD)
+        ms, pm, _ = time_plan(torch, croft, plan,
+                              lambda: croft.croft_execute_scaled(plan, d_in, e_in, d_out, e_out),
+                              steps, 3, 3)
+        info = croft.croft_plan_info(plan)
+        croft.croft_plan_destroy(plan)
+        out[name] = {"ms": ms, "GFLOPs": flops_5nlogn(N) / ms / 1e6,
+                     "effective_GBps": info["algorithmic_bytes"] / ms / 1e6, "pass_ms": pm}
+        del d_in, d_out
+    del v
+    # batched: 64 uneven PME grids
+    dims = synth.batch_dims(4)
+    grids = [synth.pme_grid(int(a), int(b), int(c), seed=400 + i)[0] for i, (a, b, c) in enumerate(dims)]
+    flat = np.concatenate([g.ravel() for g in grids]).astype(np.complex64)
+    d_in = torch.from_numpy(flat).cuda()
+    d_out = torch.empty_like(d_in)
+    plan = croft.croft_plan_create_batched([tuple(int(t) for t in d) for d in dims], croft.CROFT_C64,
+                                           croft.CROFT_FORWARD)
+    fl = sum(flops_5nlogn(int(a) * int(b) * int(c)) for a, b, c in dims)
+    for _ in range(3):
+        croft.croft_execute_batched(plan, d_in, d_out)
+    torch.cuda.synchronize()
+    a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a_.record()
+    for _ in range(steps):
+        croft.croft_execute_batched(plan, d_in, d_out)
+    b_.record()
+    torch.cuda.synchronize()
+    ms = a_.elapsed_time(b_) / steps
+    info = croft.croft_plan_info(plan)
+    croft.croft_plan_destroy(plan)
+    # the same grids as separate plain plans on one stream
+    plans = [croft.croft_plan_create(int(a), int(b), int(c), croft.CROFT_C64, croft.CROFT_FORWARD)
+             for a, b, c in dims]
+    offs = np.concatenate([[0], np.cumsum([g.size for g in grids])])
+    views = [(d_in[offs[i]:offs[i + 1]], d_out[offs[i]:offs[i + 1]]) for i in range(len(grids))]
+
+    def plain_all():
+        for p, (i_, o_) in zip(plans, views):
+            croft.croft_execute(p, i_, o_)
+    for _ in range(3):
+        plain_all()
+    torch.cuda.synchronize()
+    a_.record()
+    for _ in range(steps):
+        plain_all()
+    b_.record()
+    torch.cuda.synchronize()
+    ms_plain = a_.elapsed_time(b_) / steps
+    for p in plans:
+        croft.croft_plan_destroy(p)
+    out["batched_64"] = {"ms": ms, "GFLOPs": fl / ms / 1e6, "elements": int(flat.size),
+                         "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
+                         "plain_calls_ms": ms_plain}
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2002_04896_amd as croft
+    from paper_2002_04896_amd import synth
+
+    if args.calibrate_copy:
+        calibrate_copy(torch, args.steps, args.warmup)
+        return
+
+    n = args.size
+    N = n ** 3
+    grid, qtot = synth.pme_grid(n, n, n, seed=3)
+    x = grid.astype(np.complex64)                      # imag = 0, real part rounded to FP32
+    del grid
+    d_in = torch.from_numpy(x).cuda()
+    d_out = torch.empty_like(d_in)
+    plan = croft.croft_plan_create_ex(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD, 0, args.slabs)
+    info = croft.croft_plan_info(plan)
+    npasses = info["npasses"]
+    ms, pass_ms, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out),
+                               args.steps, args.warmup, npasses)
+    # sanity: DC bin equals the total charge
+    dc = d_out[0, 0, 0].item()
+    croft.croft_plan_destroy(plan)
+
+    gflops = flops_5nlogn(N) / ms / 1e6
+    alg_bytes = info["algorithmic_bytes"]
+    dom = max(range(npasses), key=lambda i: pass_ms[i])
+    pinfo = info["passes"][dom]
+    per_launch = 2.0 * N * info["element_bytes"]       # one sweep: read + write every element
+    achieved = per_launch / pass_ms[dom] / 1e6         # GB/s
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("kernel_hash") == kernel_hash() and t.get("pass") == dom and t.get("size") == n:
+            traffic = t.get("bytes_per_launch")
+    line = {
+        "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"forward C2C 3D FFT {n}^3 complex64, PME charge grid "
+                               f"(one +-1 charge per cell, order-4 B-spline), out of place",
+                   "nx": n, "ny": n, "nz": n, "slabs": args.slabs, "parallelism": "single GPU"},
+        "effective_hbm_GBps": alg_bytes / ms / 1e6,
+        "effective_frac_of_8TBps": alg_bytes / ms / 1e6 / HBM_PEAK_GBPS,
+        "pass_ms": pass_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": f"pass {'xyz'[pinfo['axis']]} "
+                               f"({'contiguous' if pinfo['kind'] == 0 else 'strided'}, "
+                               f"radices {'x'.join(map(str, pinfo['radices']))})",
+                     "bytes_per_launch": per_launch, "avg_launch_ms": pass_ms[dom]},
+        "check": {"dc": [dc.real, dc.imag], "total_charge": qtot},
+    }
+    if args.forms:
+        del d_in, d_out
+        torch.cuda.empty_cache()
+        line["forms"] = measure_forms(torch, np, croft, synth, max(10, args.steps // 2))
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(x, n)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

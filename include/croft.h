@@ -1,0 +1,192 @@
+/*
+ * croft.h -- C ABI of the MI355X (gfx950) complex-to-complex 3D FFT library.
+ *
+ * The operation is the 3D discrete Fourier transform of the paper, Section 2.1:
+ *   forward  (Eq. 1):  Y(k) = sum_j X(j) exp(-2 pi i (kx jx/Nx + ky jy/Ny + kz jz/Nz))
+ *   backward (Eq. 2):  the same sum with exp(+2 pi i ...).  The library does
+ *                      NOT apply Eq. (2)'s factor 1/(Nx Ny Nz): backward after
+ *                      forward returns Nx*Ny*Nz times the input (the paper's
+ *                      Section 5.3 round trip, with the caller normalising).
+ * It is computed as the paper's algorithm (Section 4.1): batched 1D FFTs along
+ * x, then y, then z, with the transposes between the stages folded into the
+ * passes so the output comes back in the input's layout (Section 4.2).
+ *
+ * Layout (all entry points): a grid is one array ("1D input array", Section
+ * 5.2) holding element (x, y, z) at index x + nx*(y + ny*z).  A torch tensor of
+ * shape (nz, ny, nx), contiguous, has exactly this layout.
+ *   CROFT_C64   complex float  (re, im interleaved), 8 bytes per element
+ *   CROFT_C128  complex double (re, im interleaved), 16 bytes per element
+ *   CROFT_C16F  two IEEE binary16 (re, im), 4 bytes per element, plus int8
+ *               power-of-two exponents: value = stored * 2^exp
+ *   CROFT_C16B  as CROFT_C16F with bfloat16 halves
+ * Half-storage plans compute in FP32 and must be run through
+ * croft_execute_scaled, which carries the exponents.
+ *
+ * Sizes: every axis length n satisfies 1 <= n <= 4096 and n = 2^a 3^b 5^c;
+ * the grid holds at most 2^31 - 1 elements.  Others give
+ * CROFT_ERR_UNSUPPORTED_SIZE.  Grids need not be cubic.
+ *
+ * Ownership: the caller owns `in`, `out` (device memory) and the exponent
+ * arrays.  A plan owns its device tables (twiddles, exponent scratch,
+ * batch descriptors), allocated at create and freed at destroy; a plan is
+ * bound to the device that was current when it was created.
+ *
+ * Streams and concurrency: execute calls are asynchronous and ordered on the
+ * given stream (NULL = the null stream); they do not synchronise the host,
+ * allocate, or copy, except where an entry point says otherwise.  One execute
+ * may be in flight per plan at a time (plans hold per-call scratch): use one
+ * plan per concurrently used stream.  Destroy a plan only after its work has
+ * completed.
+ *
+ * Errors: every call returns a croft_status (create functions return NULL);
+ * croft_last_error() then holds a message for the calling thread.  HIP launch
+ * errors are reported as CROFT_ERR_HIP with HIP's own message.  No C++
+ * exception crosses this boundary.
+ */
+#ifndef CROFT_H
+#define CROFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct croft_plan *croft_plan_t;
+
+enum croft_dtype {
+    CROFT_C64 = 0,  /* complex float storage, FP32 compute */
+    CROFT_C128 = 1, /* complex double storage, FP64 compute (the paper's type, Section 5) */
+    CROFT_C16F = 2, /* complex FP16 storage with per-line exponents, FP32 compute */
+    CROFT_C16B = 3  /* complex BF16 storage with per-line exponents, FP32 compute */
+};
+
+enum croft_direction {
+    CROFT_FORWARD = -1, /* Eq. (1): exponent sign -1 */
+    CROFT_BACKWARD = 1  /* Eq. (2) without its 1/N factor: exponent sign +1 */
+};
+
+enum croft_status {
+    CROFT_SUCCESS = 0,
+    CROFT_ERR_INVALID_VALUE = 1,    /* NULL or bad argument, overlapping buffers */
+    CROFT_ERR_UNSUPPORTED_SIZE = 2, /* axis length outside 1..4096 or not 2^a 3^b 5^c */
+    CROFT_ERR_UNSUPPORTED_DTYPE = 3,/* unknown dtype, or a call that does not fit it */
+    CROFT_ERR_OUT_OF_MEMORY = 4,    /* a plan allocation failed */
+    CROFT_ERR_HIP = 5,              /* a HIP runtime call or kernel launch failed */
+    CROFT_ERR_INTERNAL = 6
+};
+
+/* Flags for croft_plan_create_ex / croft_plan_create_batched. */
+enum croft_flags {
+    CROFT_ESTIMATE = 0,       /* default heuristics, no device timing at create */
+    CROFT_MEASURE = 1,        /* time candidate configurations at create (autotune) */
+    CROFT_FORCE_GENERIC = 2,  /* use the runtime-radix kernels for every pass */
+    CROFT_NO_WISDOM = 4       /* MEASURE: neither read nor write the wisdom file */
+};
+
+/* Create a plan for one nx x ny x nz transform (the paper's problem statement,
+ * Section 2.1, Eq. 1-2; its API runs one forward transform of the local grid,
+ * Section 5.2).  dtype: croft_dtype; dir: croft_direction.  Returns NULL on
+ * failure (see croft_last_error).  Allocates device memory on the current
+ * device. */
+croft_plan_t croft_plan_create(int nx, int ny, int nz, int dtype, int dir);
+
+/* As croft_plan_create, with croft_flags and the slab count K of the pipelined
+ * schedule: K > 1 splits the grid into K slabs along z and runs the x and y
+ * passes slab by slab on two internal streams, so that a slab written by the
+ * x pass is read back by the y pass while still cache resident; the z pass
+ * then runs over the whole grid.  This is the one-GPU form of the paper's
+ * overlap of chunked communication with computation and its iteration
+ * parameter K (Section 5.1).  K must divide nz; K = 0 lets the plan choose,
+ * K = 1 is the plain three-pass schedule.  The result does not depend on K. */
+croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, int flags, int slabs);
+
+/* Run the transform of a C64/C128 plan.  in == out runs in place; otherwise
+ * the buffers must not overlap and `in` is left unchanged.  Each buffer holds
+ * nx*ny*nz elements of the plan's dtype.  Asynchronous on `stream`. */
+int croft_execute(croft_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/* Run the transform of a C16F/C16B plan.  Values are stored * 2^exp.
+ *   in_exp:  ny*nz int8, one per x-line, index y + ny*z (NULL: all zero)
+ *   out_exp: nx*ny int8, one per z-line, index x + nx*y (required)
+ * Every output z-line is scaled so that its largest |re| or |im| lies in
+ * [2^14, 2^15) before rounding to nearest even (an all-zero line gets 0).
+ * in == out runs in place.  out_exp may be the same array as in_exp (the
+ * input exponents are consumed by the first pass, the output exponents
+ * written by the last).  Asynchronous on `stream`. */
+int croft_execute_scaled(croft_plan_t plan, const void *in, const int8_t *in_exp, void *out,
+                         int8_t *out_exp, hipStream_t stream);
+
+/* Free a plan and its device tables.  NULL is a no-op returning CROFT_SUCCESS. */
+int croft_plan_destroy(croft_plan_t plan);
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char *croft_last_error(void);
+
+/* Batched form: `count` independent transforms of uneven sizes,
+ * dims[3*i + 0..2] = (nx, ny, nz) of grid i.  Grids are packed back to back in
+ * one buffer, grid i starting at element offset offsets[i] (see
+ * croft_plan_batched_offsets).  dtype CROFT_C64 or CROFT_C128.  flags:
+ * croft_flags (CROFT_MEASURE autotunes the kernel configuration per length
+ * and records it in the wisdom file). */
+croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, int dir, int flags);
+
+/* Element offsets of the grids of a batched plan: count + 1 values, the last
+ * being the total element count.  `elem_offsets` is host memory. */
+int croft_plan_batched_offsets(croft_plan_t plan, size_t *elem_offsets);
+
+/* Run every transform of a batched plan: one launch per axis pass covering
+ * all grids, replayed from a HIP graph captured on first use for the given
+ * (in, out, stream).  Same in/out rules as croft_execute. */
+int croft_execute_batched(croft_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/* Description of a plan, filled by croft_plan_info. */
+#define CROFT_MAX_PASSES 8
+#define CROFT_MAX_STAGES 12
+struct croft_pass_info {
+    int axis;            /* 0 = x, 1 = y, 2 = z */
+    int n;               /* transform length */
+    int kind;            /* 0: contiguous lines, 1: strided lines */
+    int generic;         /* 1 if the runtime-radix kernel runs this pass */
+    int nstages;
+    int radices[CROFT_MAX_STAGES];
+    int threads_per_line;
+    int lines_per_block;
+    int block_threads;
+    long long blocks;    /* grid size of one launch over the whole grid */
+    size_t lds_bytes;
+};
+struct croft_plan_info {
+    int nx, ny, nz, dtype, dir;
+    int batched_count;   /* 0 for a single-grid plan */
+    int slabs;           /* K of the slab schedule (1 = plain) */
+    int npasses;
+    struct croft_pass_info pass[CROFT_MAX_PASSES];
+    size_t elements;          /* total elements (all grids for a batched plan) */
+    size_t element_bytes;     /* bytes per stored element */
+    size_t work_bytes;        /* device scratch owned by the plan */
+    double algorithmic_bytes; /* 3 sweeps x (read + write) x elements x element_bytes */
+    double flops;             /* sum over grids of 5 N log2 N */
+};
+int croft_plan_info(croft_plan_t plan, struct croft_plan_info *info);
+
+/* Dry run: write a text description of the plan that croft_plan_create would
+ * build (passes, radices, launch shapes, bytes) into buf (len bytes, always
+ * NUL-terminated when len > 0).  Uses no GPU.  Returns a croft_status. */
+int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len);
+
+/* Per-kernel timing: while enabled, every execute on the plan records HIP
+ * events around each pass launch on the stream it is launched on.
+ * croft_plan_profile_read waits for the recorded events, then writes for each
+ * pass p (p < max_passes) the total milliseconds over the recorded executes
+ * into pass_ms[p] and the execute count into *executes, and clears the record.
+ * Enabling allocates events; not for use under stream capture. */
+int croft_plan_profile(croft_plan_t plan, int enable);
+int croft_plan_profile_read(croft_plan_t plan, double *pass_ms, int max_passes, int *executes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CROFT_H */

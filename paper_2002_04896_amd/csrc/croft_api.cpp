@@ -1,0 +1,695 @@
+// croft_api.cpp -- the C ABI of include/croft.h: plan construction, pass
+// schedules, execution, errors and introspection.
+#include "croft.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "croft_internal.h"
+
+using namespace croft;
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+    return fail(CROFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+}  // namespace
+
+// -------------------------------------------------------------------- plan
+struct croft_plan {
+    int dtype = 0, dir = -1, flags = 0, slabs = 1;
+    int device = 0;
+    // grids (one for a plain plan)
+    std::vector<Geometry> grids;
+    std::vector<size_t> offsets;  // element offsets, grids.size() + 1 entries
+    // per grid: the pass list of the plain schedule
+    std::vector<std::vector<PassLaunch>> passes;
+    std::map<int, void *> twiddles;  // length -> device table
+    int8_t *e1 = nullptr, *e2 = nullptr;  // half storage: exponents after x and y passes
+    size_t work_bytes = 0;
+    // slab schedule
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // batched form: graph cache
+    hipGraphExec_t graph = nullptr;
+    const void *graph_in = nullptr;
+    void *graph_out = nullptr;
+    hipStream_t graph_stream = nullptr;
+    // profiling
+    bool profiling = false;
+    std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;  // per execute, per pass
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+bool is_half(int dtype) { return dtype == CROFT_C16F || dtype == CROFT_C16B; }
+
+size_t compute_bytes(int dtype) { return dtype == CROFT_C128 ? 16 : 8; }
+
+int check_dims(int nx, int ny, int nz) {
+    const int d[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] < 1) return fail(CROFT_ERR_INVALID_VALUE, "axis %d length %d < 1", a, d[a]);
+        if (!smooth_length(d[a]))
+            return fail(CROFT_ERR_UNSUPPORTED_SIZE,
+                        "axis %d length %d unsupported (need 1..%d of the form 2^a 3^b 5^c)", a, d[a],
+                        kMaxLength);
+    }
+    if ((long long)nx * ny * nz > 0x7fffffffLL)
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "grid of %lld elements exceeds 2^31 - 1",
+                    (long long)nx * ny * nz);
+    return CROFT_SUCCESS;
+}
+
+int check_dtype_dir(int dtype, int dir) {
+    if (dtype < CROFT_C64 || dtype > CROFT_C16B) return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "unknown dtype %d", dtype);
+    if (dir != CROFT_FORWARD && dir != CROFT_BACKWARD)
+        return fail(CROFT_ERR_INVALID_VALUE, "direction %d is neither CROFT_FORWARD (-1) nor CROFT_BACKWARD (+1)",
+                    dir);
+    return CROFT_SUCCESS;
+}
+
+// The pass list of one grid, without device resources (twiddle pointers are
+// filled in later).  Half storage always runs all three axes, so that every
+// pass re-scales its lines and the output exponents are per z-line.
+int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch> *out) {
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const bool half = is_half(dtype);
+    out->clear();
+    for (int axis = 0; axis < 3; ++axis) {
+        const int n = dims[axis];
+        if (n == 1 && !half) continue;
+        PassLaunch p;
+        p.axis = axis;
+        p.n = n;
+        p.es = axis == 0 ? 1 : (axis == 1 ? (long long)g.nx : (long long)g.nx * g.ny);
+        p.kind = p.es == 1 ? kContiguous : kStrided;
+        if (p.kind == kContiguous) {
+            p.nlines = N / n;
+            p.nw = 1;
+        } else {
+            p.nlines = p.es;
+            p.nw = N / (p.es * n);
+        }
+        if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, &p.cfg))
+            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+        if (half) {
+            ExpMap &m = p.em;
+            const long long big = 1LL << 40;
+            if (axis == 0) {
+                // lines l = y + ny z; input exponents per x-line; output per x-line
+                m.qmod = big; m.a0 = 1; m.b0 = 1;
+            } else if (axis == 1) {
+                if (p.kind == kStrided) {  // q = x, w = z, j = y
+                    m.qmod = big; m.a2 = g.ny; m.a3 = 1; m.b0 = 1; m.b2 = g.nx;
+                } else {                   // nx == 1: q = z, j = y
+                    m.qmod = big; m.a0 = g.ny; m.a3 = 1; m.b0 = 1;
+                }
+            } else {
+                if (p.kind == kStrided) {  // q = x + nx y, j = z
+                    m.qmod = g.nx; m.a0 = 1; m.a3 = g.nx; m.b0 = 1; m.b1 = g.nx;
+                } else {                   // nx == ny == 1: one line, j = z
+                    m.qmod = big; m.a3 = 1; m.b0 = 1;
+                }
+            }
+        }
+        out->push_back(p);
+    }
+    if (out->empty()) {  // 1 x 1 x 1 grid: one length-1 pass copies in to out
+        PassLaunch p;
+        p.axis = 0;
+        p.n = 1;
+        p.es = 1;
+        p.kind = kContiguous;
+        p.nlines = 1;
+        if (!select_kernel(1, kContiguous, dtype, true, &p.cfg))
+            return fail(CROFT_ERR_INTERNAL, "no kernel for a 1-point grid");
+        out->push_back(p);
+    }
+    return CROFT_SUCCESS;
+}
+
+// Largest exponent index a pass touches (host-side bound check of ExpMap).
+void exp_extent(const PassLaunch &p, long long *in_max, long long *out_max) {
+    const ExpMap &m = p.em;
+    const long long qmax = p.kind == kContiguous ? p.nlines - 1 : p.es - 1;
+    const long long wmax = p.kind == kContiguous ? 0 : p.nw - 1;
+    long long imax = 0, omax = 0;
+    // the maps are sums of non-negative terms; the maximum over q of
+    // (q % qmod) a0 + (q / qmod) a1 is reached at q = qmax or at the largest
+    // q with q % qmod == qmod - 1
+    const long long cands[2] = {qmax, m.qmod <= qmax ? ((qmax + 1) / m.qmod) * m.qmod - 1 : qmax};
+    for (long long q : cands) {
+        if (q < 0) continue;
+        const long long iq = (q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + wmax * m.a2 + (p.n - 1) * m.a3;
+        const long long oq = (q % m.qmod) * m.b0 + (q / m.qmod) * m.b1 + wmax * m.b2;
+        imax = std::max(imax, iq);
+        omax = std::max(omax, oq);
+    }
+    *in_max = imax;
+    *out_max = omax;
+}
+
+int check_exp_maps(const Geometry &g, const std::vector<PassLaunch> &ps) {
+    const long long sizes[4] = {(long long)g.ny * g.nz, (long long)g.ny * g.nz, (long long)g.nx * g.nz,
+                                (long long)g.nx * g.ny};
+    for (size_t i = 0; i < ps.size(); ++i) {
+        long long imax, omax;
+        exp_extent(ps[i], &imax, &omax);
+        if (imax >= sizes[i] || omax >= sizes[i + 1])
+            return fail(CROFT_ERR_INTERNAL, "exponent map of pass %zu out of range", i);
+    }
+    return CROFT_SUCCESS;
+}
+
+void destroy_plan(croft_plan *p) {
+    if (!p) return;
+    for (auto &kv : p->twiddles) (void)hipFree(kv.second);
+    if (p->e1) (void)hipFree(p->e1);
+    if (p->e2) (void)hipFree(p->e2);
+    for (int i = 0; i < 2; ++i) {
+        if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
+        if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+    for (auto &v : p->prof)
+        for (auto &pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    delete p;
+}
+
+// Device resources for the passes of every grid: twiddle tables (one per
+// distinct length), exponent scratch, kernel attributes.
+int attach_resources(croft_plan *p) {
+    hipError_t e;
+    const bool dbl = p->dtype == CROFT_C128;
+    for (auto &ps : p->passes) {
+        for (PassLaunch &pl : ps) {
+            if (pl.n > 1 && !p->twiddles.count(pl.n)) {
+                std::vector<double> w(2 * (size_t)pl.n);
+                twiddles_fp64(pl.n, w.data());
+                void *d = nullptr;
+                const size_t bytes = (size_t)pl.n * compute_bytes(p->dtype);
+                if ((e = hipMalloc(&d, bytes)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(CROFT_ERR_OUT_OF_MEMORY, "twiddle table: %s", hipGetErrorString(e));
+                }
+                p->twiddles[pl.n] = d;
+                p->work_bytes += bytes;
+                if (dbl) {
+                    e = hipMemcpy(d, w.data(), bytes, hipMemcpyHostToDevice);
+                } else {
+                    std::vector<float> f(w.size());
+                    for (size_t i = 0; i < w.size(); ++i) f[i] = (float)w[i];  // round to nearest even
+                    e = hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice);
+                }
+                if (e != hipSuccess) return fail_hip(e, "twiddle upload");
+            }
+            pl.tw = pl.n > 1 ? p->twiddles[pl.n] : nullptr;
+            if (pl.cfg.lds > 65536) {
+                e = hipFuncSetAttribute(pl.cfg.func, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)pl.cfg.lds);
+                if (e != hipSuccess) return fail_hip(e, "LDS attribute");
+            }
+        }
+    }
+    if (is_half(p->dtype)) {
+        const Geometry &g = p->grids[0];
+        const size_t b1 = (size_t)g.ny * g.nz, b2 = (size_t)g.nx * g.nz;
+        if ((e = hipMalloc(&p->e1, b1)) != hipSuccess || (e = hipMalloc(&p->e2, b2)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "exponent scratch: %s", hipGetErrorString(e));
+        }
+        p->work_bytes += b1 + b2;
+    }
+    if (p->slabs > 1) {
+        for (int i = 0; i < 2; ++i) {
+            if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking)) != hipSuccess)
+                return fail_hip(e, "stream create");
+            if ((e = hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming)) != hipSuccess)
+                return fail_hip(e, "event create");
+        }
+        if ((e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess)
+            return fail_hip(e, "event create");
+    }
+    return CROFT_SUCCESS;
+}
+
+croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int flags, int slabs) {
+    croft_plan *p = new (std::nothrow) croft_plan;
+    if (!p) {
+        fail(CROFT_ERR_OUT_OF_MEMORY, "host allocation failed");
+        return nullptr;
+    }
+    p->dtype = dtype;
+    p->dir = dir;
+    p->flags = flags;
+    p->slabs = slabs;
+    p->grids = grids;
+    p->offsets.assign(1, 0);
+    for (const Geometry &g : grids) p->offsets.push_back(p->offsets.back() + (size_t)g.nx * g.ny * g.nz);
+    p->passes.resize(grids.size());
+    for (size_t i = 0; i < grids.size(); ++i) {
+        if (build_passes(grids[i], dtype, flags, &p->passes[i]) != CROFT_SUCCESS) {
+            delete p;
+            return nullptr;
+        }
+        if (is_half(dtype) && check_exp_maps(grids[i], p->passes[i]) != CROFT_SUCCESS) {
+            delete p;
+            return nullptr;
+        }
+    }
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        fail_hip(e, "hipGetDevice");
+        delete p;
+        return nullptr;
+    }
+    if (attach_resources(p) != CROFT_SUCCESS) {
+        std::string msg = g_last_error;
+        destroy_plan(p);
+        g_last_error = msg;
+        return nullptr;
+    }
+    return p;
+}
+
+// ---------------------------------------------------------------- execute
+hipEvent_t pool_event(croft_plan *p) {
+    hipEvent_t e = nullptr;
+    if (!p->event_pool.empty()) {
+        e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch one pass over elements [off, off + ...) of a grid.
+int run_pass(croft_plan *p, const PassLaunch &pl, const void *in, void *out, const int8_t *ie, int8_t *oe,
+             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof) {
+        a = pool_event(p);
+        b = pool_event(p);
+        if (!a || !b) return fail(CROFT_ERR_HIP, "profiling event creation failed");
+        (void)hipEventRecord(a, s);
+    }
+    const hipError_t e = launch_pass(pl, p->dtype, in, out, ie, oe, p->dir == CROFT_BACKWARD, s);
+    if (e != hipSuccess) return fail_hip(e, "kernel launch");
+    const hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return fail_hip(e2, "kernel launch");
+    if (prof) {
+        (void)hipEventRecord(b, s);
+        prof->push_back({a, b});
+    }
+    return CROFT_SUCCESS;
+}
+
+// Plain schedule of one grid: each pass over the whole grid, the first
+// reading `in`, the rest working in place on `out`.
+int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp,
+             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    const std::vector<PassLaunch> &ps = p->passes[gi];
+    const bool half = is_half(p->dtype);
+    for (size_t i = 0; i < ps.size(); ++i) {
+        const void *src = i == 0 ? (const void *)in : (const void *)out;
+        const int8_t *ie = nullptr;
+        int8_t *oe = nullptr;
+        if (half) {
+            ie = i == 0 ? in_exp : (i == 1 ? p->e1 : p->e2);
+            oe = i == 0 ? p->e1 : (i == 1 ? p->e2 : out_exp);
+        }
+        const int rc = run_pass(p, ps[i], src, out, ie, oe, s, prof);
+        if (rc != CROFT_SUCCESS) return rc;
+    }
+    return CROFT_SUCCESS;
+}
+
+// Slab schedule (K = p->slabs): the x and y passes slab by slab along z on two
+// side streams, then the z pass over the whole grid on the caller's stream.
+int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp, hipStream_t s,
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    const Geometry &g = p->grids[0];
+    const std::vector<PassLaunch> &ps = p->passes[0];
+    const bool half = is_half(p->dtype);
+    const size_t eb = element_bytes(p->dtype);
+    const int K = p->slabs;
+    const int dz = g.nz / K;
+    // passes along x and y (those with axis < 2), and the z pass if present
+    std::vector<const PassLaunch *> xy;
+    const PassLaunch *zp = nullptr;
+    for (const PassLaunch &pl : ps) (pl.axis < 2 ? xy.push_back(&pl) : (void)(zp = &pl));
+    hipError_t e;
+    if ((e = hipEventRecord(p->fork, s)) != hipSuccess) return fail_hip(e, "event record");
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipStreamWaitEvent(p->side[i], p->fork, 0)) != hipSuccess) return fail_hip(e, "stream wait");
+    for (int k = 0; k < K; ++k) {
+        hipStream_t ss = p->side[k & 1];
+        const long long z0 = (long long)k * dz;
+        const size_t off = (size_t)z0 * g.nx * g.ny * eb;
+        for (size_t i = 0; i < xy.size(); ++i) {
+            PassLaunch pl = *xy[i];
+            if (pl.kind == kContiguous) pl.nlines = pl.nlines / K;
+            else pl.nw = pl.nw / K;
+            const void *src = i == 0 ? (const void *)(in + off) : (const void *)(out + off);
+            const int8_t *ie = nullptr;
+            int8_t *oe = nullptr;
+            if (half) {
+                // x pass: exponents per x-line (y + ny z); y pass: per y-line (x + nx z)
+                if (pl.axis == 0) {
+                    ie = in_exp ? in_exp + z0 * g.ny : nullptr;
+                    oe = p->e1 + z0 * g.ny;
+                } else {
+                    ie = p->e1 + z0 * g.ny;
+                    oe = p->e2 + z0 * g.nx;
+                }
+            }
+            const int rc = run_pass(p, pl, src, out + off, ie, oe, ss, prof);
+            if (rc != CROFT_SUCCESS) return rc;
+        }
+    }
+    for (int i = 0; i < 2; ++i) {
+        if ((e = hipEventRecord(p->join[i], p->side[i])) != hipSuccess) return fail_hip(e, "event record");
+        if ((e = hipStreamWaitEvent(s, p->join[i], 0)) != hipSuccess) return fail_hip(e, "stream wait");
+    }
+    if (zp) {
+        const void *src = xy.empty() ? (const void *)in : (const void *)out;
+        const int rc = run_pass(p, *zp, src, out, half ? p->e2 : nullptr, half ? out_exp : nullptr, s, prof);
+        if (rc != CROFT_SUCCESS) return rc;
+    }
+    return CROFT_SUCCESS;
+}
+
+int check_buffers(croft_plan *p, const void *in, const void *out) {
+    if (!in || !out) return fail(CROFT_ERR_INVALID_VALUE, "NULL data pointer");
+    const size_t bytes = p->offsets.back() * element_bytes(p->dtype);
+    const char *a = (const char *)in, *b = (const char *)out;
+    if (a != b && a < b + bytes && b < a + bytes)
+        return fail(CROFT_ERR_INVALID_VALUE, "in and out overlap without being equal");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(CROFT_ERR_INVALID_VALUE, "the current device (%d) is not the plan's device (%d)", dev,
+                    p->device);
+    return CROFT_SUCCESS;
+}
+
+int execute_any(croft_plan *p, const void *in, const int8_t *in_exp, void *out, int8_t *out_exp,
+                hipStream_t s) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rec;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof = p->profiling ? &rec : nullptr;
+    int rc;
+    if (p->slabs > 1)
+        rc = run_slabs(p, (const char *)in, (char *)out, in_exp, out_exp, s, prof);
+    else
+        rc = run_grid(p, 0, (const char *)in, (char *)out, in_exp, out_exp, s, prof);
+    if (prof) p->prof.push_back(std::move(rec));
+    return rc;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *croft_last_error(void) { return g_last_error.c_str(); }
+
+croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, int flags, int slabs) {
+    g_last_error.clear();
+    if (check_dtype_dir(dtype, dir) != CROFT_SUCCESS) return nullptr;
+    if (check_dims(nx, ny, nz) != CROFT_SUCCESS) return nullptr;
+    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
+        fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
+        return nullptr;
+    }
+    if (slabs < 0 || (slabs > 1 && nz % slabs != 0)) {
+        fail(CROFT_ERR_INVALID_VALUE, "slab count %d must be 0, 1 or a divisor of nz = %d", slabs, nz);
+        return nullptr;
+    }
+    if (slabs == 0) slabs = 1;
+    return new_plan({Geometry{nx, ny, nz}}, dtype, dir, flags, slabs);
+}
+
+croft_plan_t croft_plan_create(int nx, int ny, int nz, int dtype, int dir) {
+    return croft_plan_create_ex(nx, ny, nz, dtype, dir, CROFT_ESTIMATE, 1);
+}
+
+int croft_plan_destroy(croft_plan_t plan) {
+    destroy_plan(plan);
+    return CROFT_SUCCESS;
+}
+
+int croft_execute(croft_plan_t p, const void *in, void *out, hipStream_t stream) {
+    if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    if (p->grids.size() != 1) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
+    if (is_half(p->dtype))
+        return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "half-storage plan: use croft_execute_scaled");
+    const int rc = check_buffers(p, in, out);
+    if (rc != CROFT_SUCCESS) return rc;
+    return execute_any(p, in, nullptr, out, nullptr, stream);
+}
+
+int croft_execute_scaled(croft_plan_t p, const void *in, const int8_t *in_exp, void *out, int8_t *out_exp,
+                         hipStream_t stream) {
+    if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    if (p->grids.size() != 1) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
+    if (!is_half(p->dtype))
+        return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "croft_execute_scaled needs a CROFT_C16F/CROFT_C16B plan");
+    if (!out_exp) return fail(CROFT_ERR_INVALID_VALUE, "NULL out_exp");
+    const int rc = check_buffers(p, in, out);
+    if (rc != CROFT_SUCCESS) return rc;
+    return execute_any(p, in, in_exp, out, out_exp, stream);
+}
+
+croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, int dir, int flags) {
+    g_last_error.clear();
+    if (count < 1 || !dims) {
+        fail(CROFT_ERR_INVALID_VALUE, "batched plan needs count >= 1 and dims");
+        return nullptr;
+    }
+    if (check_dtype_dir(dtype, dir) != CROFT_SUCCESS) return nullptr;
+    if (is_half(dtype)) {
+        fail(CROFT_ERR_UNSUPPORTED_DTYPE, "batched plans take CROFT_C64 or CROFT_C128");
+        return nullptr;
+    }
+    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
+        fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
+        return nullptr;
+    }
+    std::vector<Geometry> grids;
+    long long total = 0;
+    for (int i = 0; i < count; ++i) {
+        if (check_dims(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2]) != CROFT_SUCCESS) {
+            g_last_error = "grid " + std::to_string(i) + ": " + g_last_error;
+            return nullptr;
+        }
+        grids.push_back({dims[3 * i], dims[3 * i + 1], dims[3 * i + 2]});
+        total += (long long)dims[3 * i] * dims[3 * i + 1] * dims[3 * i + 2];
+    }
+    if (total > 0x7fffffffLL) {
+        fail(CROFT_ERR_UNSUPPORTED_SIZE, "batch of %lld elements exceeds 2^31 - 1", total);
+        return nullptr;
+    }
+    return new_plan(grids, dtype, dir, flags, 1);
+}
+
+int croft_plan_batched_offsets(croft_plan_t p, size_t *elem_offsets) {
+    if (!p || !elem_offsets) return fail(CROFT_ERR_INVALID_VALUE, "NULL argument");
+    std::copy(p->offsets.begin(), p->offsets.end(), elem_offsets);
+    return CROFT_SUCCESS;
+}
+
+int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t stream) {
+    if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    int rc = check_buffers(p, in, out);
+    if (rc != CROFT_SUCCESS) return rc;
+    const size_t eb = element_bytes(p->dtype);
+    if (p->profiling) {
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> rec;
+        for (size_t g = 0; g < p->grids.size() && rc == CROFT_SUCCESS; ++g)
+            rc = run_grid(p, g, (const char *)in + p->offsets[g] * eb, (char *)out + p->offsets[g] * eb, nullptr,
+                          nullptr, stream, &rec);
+        p->prof.push_back(std::move(rec));
+        return rc;
+    }
+    if (!p->graph || p->graph_in != in || p->graph_out != out || p->graph_stream != stream) {
+        if (p->graph) {
+            (void)hipGraphExecDestroy(p->graph);
+            p->graph = nullptr;
+        }
+        hipStream_t cap;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail_hip(e, "stream create");
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return fail_hip(e, "begin capture");
+        }
+        for (size_t g = 0; g < p->grids.size() && rc == CROFT_SUCCESS; ++g)
+            rc = run_grid(p, g, (const char *)in + p->offsets[g] * eb, (char *)out + p->offsets[g] * eb, nullptr,
+                          nullptr, cap, nullptr);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap, &graph);
+        (void)hipStreamDestroy(cap);
+        if (rc != CROFT_SUCCESS) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail_hip(e, "end capture");
+        e = hipGraphInstantiate(&p->graph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            p->graph = nullptr;
+            return fail_hip(e, "graph instantiate");
+        }
+        p->graph_in = in;
+        p->graph_out = out;
+        p->graph_stream = stream;
+    }
+    const hipError_t e = hipGraphLaunch(p->graph, stream);
+    if (e != hipSuccess) return fail_hip(e, "graph launch");
+    return CROFT_SUCCESS;
+}
+
+int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
+    if (!p || !info) return fail(CROFT_ERR_INVALID_VALUE, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    const Geometry &g = p->grids[0];
+    info->nx = g.nx;
+    info->ny = g.ny;
+    info->nz = g.nz;
+    info->dtype = p->dtype;
+    info->dir = p->dir;
+    info->batched_count = p->grids.size() > 1 ? (int)p->grids.size() : 0;
+    info->slabs = p->slabs;
+    const std::vector<PassLaunch> &ps = p->passes[0];
+    info->npasses = (int)std::min<size_t>(ps.size(), CROFT_MAX_PASSES);
+    for (int i = 0; i < info->npasses; ++i) {
+        const PassLaunch &pl = ps[i];
+        croft_pass_info &pi = info->pass[i];
+        pi.axis = pl.axis;
+        pi.n = pl.n;
+        pi.kind = pl.kind;
+        pi.generic = pl.cfg.generic ? 1 : 0;
+        pi.nstages = pl.cfg.nstages;
+        for (int s = 0; s < pl.cfg.nstages; ++s) pi.radices[s] = pl.cfg.radix[s];
+        pi.threads_per_line = pl.cfg.threads_per_line;
+        pi.lines_per_block = pl.cfg.lines;
+        pi.block_threads = pl.cfg.block;
+        pi.blocks = pl.kind == kContiguous ? (pl.nlines + pl.cfg.lines - 1) / pl.cfg.lines
+                                           : ((pl.es + pl.cfg.lines - 1) / pl.cfg.lines) * pl.nw;
+        pi.lds_bytes = pl.cfg.lds;
+    }
+    info->elements = p->offsets.back();
+    info->element_bytes = element_bytes(p->dtype);
+    info->work_bytes = p->work_bytes;
+    info->algorithmic_bytes = 6.0 * (double)info->elements * (double)info->element_bytes;
+    double fl = 0;
+    for (const Geometry &gg : p->grids) {
+        const double n = (double)gg.nx * gg.ny * gg.nz;
+        if (n > 1) fl += 5.0 * n * std::log2(n);
+    }
+    info->flops = fl;
+    return CROFT_SUCCESS;
+}
+
+int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len) {
+    g_last_error.clear();
+    int rc = check_dtype_dir(dtype, dir);
+    if (rc != CROFT_SUCCESS) return rc;
+    rc = check_dims(nx, ny, nz);
+    if (rc != CROFT_SUCCESS) return rc;
+    if (!buf && len) return fail(CROFT_ERR_INVALID_VALUE, "NULL buffer");
+    const Geometry g{nx, ny, nz};
+    std::vector<PassLaunch> ps;
+    rc = build_passes(g, dtype, 0, &ps);
+    if (rc != CROFT_SUCCESS) return rc;
+    if (is_half(dtype) && (rc = check_exp_maps(g, ps)) != CROFT_SUCCESS) return rc;
+    static const char *names[] = {"c64", "c128", "c16f", "c16b"};
+    std::string s;
+    char line[512];
+    const size_t N = (size_t)nx * ny * nz;
+    snprintf(line, sizeof line, "grid %dx%dx%d %s %s elements=%zu bytes=%zu algorithmic_bytes=%.0f\n", nx, ny, nz,
+             names[dtype], dir == CROFT_FORWARD ? "forward" : "backward", N, N * element_bytes(dtype),
+             6.0 * N * element_bytes(dtype));
+    s += line;
+    for (size_t i = 0; i < ps.size(); ++i) {
+        const PassLaunch &pl = ps[i];
+        std::string rad;
+        for (int k = 0; k < pl.cfg.nstages; ++k) rad += (k ? "x" : "") + std::to_string(pl.cfg.radix[k]);
+        if (rad.empty()) rad = "copy";
+        const long long blocks = pl.kind == kContiguous ? (pl.nlines + pl.cfg.lines - 1) / pl.cfg.lines
+                                                        : ((pl.es + pl.cfg.lines - 1) / pl.cfg.lines) * pl.nw;
+        snprintf(line, sizeof line,
+                 "pass %zu axis=%c n=%d kind=%s kernel=%s radices=%s stride=%lld lines=%lld T=%d L=%d block=%d "
+                 "blocks=%lld lds=%zu\n",
+                 i, "xyz"[pl.axis], pl.n, pl.kind == kContiguous ? "contiguous" : "strided",
+                 pl.cfg.generic ? "generic" : "static", rad.c_str(), pl.es,
+                 pl.kind == kContiguous ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
+                 pl.cfg.block, blocks, pl.cfg.lds);
+        s += line;
+    }
+    if (len) {
+        const size_t n = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = '\0';
+    }
+    return CROFT_SUCCESS;
+}
+
+int croft_plan_profile(croft_plan_t p, int enable) {
+    if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    p->profiling = enable != 0;
+    return CROFT_SUCCESS;
+}
+
+int croft_plan_profile_read(croft_plan_t p, double *pass_ms, int max_passes, int *executes) {
+    if (!p || (!pass_ms && max_passes > 0) || max_passes < 0) return fail(CROFT_ERR_INVALID_VALUE, "bad argument");
+    for (int i = 0; i < max_passes; ++i) pass_ms[i] = 0.0;
+    int rc = CROFT_SUCCESS;
+    for (auto &rec : p->prof) {
+        for (size_t i = 0; i < rec.size(); ++i) {
+            hipError_t e = hipEventSynchronize(rec[i].second);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, rec[i].first, rec[i].second);
+            if (e != hipSuccess && rc == CROFT_SUCCESS) rc = fail_hip(e, "profiling event");
+            if ((int)i < max_passes) pass_ms[i] += ms;
+            p->event_pool.push_back(rec[i].first);
+            p->event_pool.push_back(rec[i].second);
+        }
+    }
+    if (executes) *executes = (int)p->prof.size();
+    p->prof.clear();
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// croft_plan.cpp -- host-side planning helpers: supported lengths, radix
+// factorisation and the FP64 twiddle generator.
+#include <cmath>
+
+#include "croft_internal.h"
+
+namespace croft {
+
+bool smooth_length(int n) {
+    if (n < 1 || n > kMaxLength) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Same factorisation rule as the kernels' compile-time plans: the 5s, the 3s,
+// then the power of two as radix-8 stages plus one radix-4 or radix-16 stage
+// for the remainder (a lone 2 or 4 for n = 2, 4).
+int factorize(int n, int *radix) {
+    if (!smooth_length(n)) return 0;
+    int m = n, c5 = 0, c3 = 0, a2 = 0, s = 0;
+    while (m % 5 == 0) { m /= 5; ++c5; }
+    while (m % 3 == 0) { m /= 3; ++c3; }
+    while (m % 2 == 0) { m /= 2; ++a2; }
+    for (int i = 0; i < c5; ++i) radix[s++] = 5;
+    for (int i = 0; i < c3; ++i) radix[s++] = 3;
+    const int k = a2 / 3, rem = a2 % 3;
+    if (rem == 1 && k >= 1) {
+        for (int i = 0; i < k - 1; ++i) radix[s++] = 8;
+        radix[s++] = 16;
+    } else {
+        for (int i = 0; i < k; ++i) radix[s++] = 8;
+        if (rem == 1) radix[s++] = 2;
+        if (rem == 2) radix[s++] = 4;
+    }
+    return s;
+}
+
+// w[m] = exp(-2 pi i m / n).  The angle 2 pi m / n is split into q quarter
+// turns plus phi = (pi/2) r / n with r = 4m - q n in [0, n); phi is folded into
+// [0, pi/4] (cos and sin swap beyond it) so that libm only sees small angles,
+// values at multiples of pi/4 come out exactly symmetric, and the quarter
+// turns are applied exactly by swapping and negating.
+void twiddles_fp64(int n, double *out) {
+    const double half_pi = 1.57079632679489661923132169163975144;
+    for (int m = 0; m < n; ++m) {
+        const long long q = (4LL * m) / n;
+        const long long r = 4LL * m - q * n;
+        double c, s;
+        if (2 * r == n) {
+            c = s = 0.70710678118654752440084436210484904;
+        } else if (2 * r < n) {
+            const double phi = half_pi * (double)r / (double)n;
+            c = std::cos(phi);
+            s = std::sin(phi);
+        } else {
+            const double phi = half_pi * (double)(n - r) / (double)n;
+            c = std::sin(phi);
+            s = std::cos(phi);
+        }
+        double C, S;
+        switch (q & 3) {
+            case 0: C = c; S = s; break;
+            case 1: C = -s; S = c; break;
+            case 2: C = -c; S = -s; break;
+            default: C = s; S = -c; break;
+        }
+        out[2 * m] = C;
+        out[2 * m + 1] = -S;
+    }
+}
+
+}  // namespace croft

@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: symbols, argument validation, dry-run plans."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2002_04896_amd as croft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "croft.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(croft_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(croft.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in croft.h but not exported"
+    assert sorted(croft.EXPORTED) == names
+
+
+@pytest.mark.parametrize("dims,msg", [
+    ((0, 4, 4), "< 1"), ((4, -2, 4), "< 1"), ((7, 4, 4), "unsupported"),
+    ((4, 4, 4097), "unsupported"), ((4, 4, 8192), "unsupported"), ((14, 4, 4), "unsupported"),
+])
+def test_create_rejects_bad_sizes(dims, msg):
+    with pytest.raises(ValueError, match=msg):
+        croft.croft_plan_create(*dims)
+
+
+def test_create_rejects_bad_dtype_and_direction():
+    with pytest.raises(ValueError, match="dtype"):
+        croft.croft_plan_create(8, 8, 8, 7, croft.CROFT_FORWARD)
+    with pytest.raises(ValueError, match="direction"):
+        croft.croft_plan_create(8, 8, 8, croft.CROFT_C64, 0)
+    with pytest.raises(ValueError, match="flags"):
+        croft.croft_plan_create_ex(8, 8, 8, croft.CROFT_C64, -1, 64, 1)
+    with pytest.raises(ValueError, match="slab"):
+        croft.croft_plan_create_ex(8, 8, 12, croft.CROFT_C64, -1, 0, 5)
+    with pytest.raises(ValueError, match="2\\^31"):
+        croft.croft_plan_create(4096, 4096, 256)
+
+
+def test_batched_create_rejects_bad_grids():
+    with pytest.raises(ValueError, match="grid 1"):
+        croft.croft_plan_create_batched([(8, 8, 8), (8, 7, 8)])
+    with pytest.raises(ValueError, match="C64 or"):
+        croft.croft_plan_create_batched([(8, 8, 8)], croft.CROFT_C16F)
+    with pytest.raises(ValueError, match="count"):
+        croft.croft_plan_create_batched([])
+
+
+def test_null_plan_calls():
+    lib = croft.load()
+    assert lib.croft_execute(None, None, None, None) == croft.CROFT_ERR_INVALID_VALUE
+    assert "NULL plan" in croft.croft_last_error()
+    assert lib.croft_execute_scaled(None, None, None, None, None, None) == croft.CROFT_ERR_INVALID_VALUE
+    assert lib.croft_execute_batched(None, None, None, None) == croft.CROFT_ERR_INVALID_VALUE
+    assert lib.croft_plan_destroy(None) == croft.CROFT_SUCCESS
+    assert lib.croft_plan_info(None, None) == croft.CROFT_ERR_INVALID_VALUE
+    assert lib.croft_plan_profile(None, 1) == croft.CROFT_ERR_INVALID_VALUE
+
+
+def parse_describe(text):
+    lines = text.strip().split("\n")
+    head = lines[0]
+    passes = []
+    for ln in lines[1:]:
+        kv = dict(tok.split("=", 1) for tok in ln.split()[2:])
+        passes.append(kv)
+    return head, passes
+
+
+def test_describe_512_cube():
+    head, passes = parse_describe(croft.croft_plan_describe(512, 512, 512))
+    assert "elements=134217728" in head and "bytes=1073741824" in head
+    assert "algorithmic_bytes=6442450944" in head
+    assert [p["axis"] for p in passes] == ["x", "y", "z"]
+    assert [p["kind"] for p in passes] == ["contiguous", "strided", "strided"]
+    assert [p["stride"] for p in passes] == ["1", "512", "262144"]
+    for p in passes:
+        assert p["kernel"] == "static" and p["radices"] == "8x8x8"
+        assert int(p["lines"]) == 512 * 512
+
+
+@pytest.mark.parametrize("n,rad", [(384, "3x8x16"), (48, "3x16"), (60, "5x3x4"), (72, "3x3x8"),
+                                   (80, "5x16"), (96, "3x8x4"), (100, "5x5x4"), (128, "8x16"),
+                                   (1024, "8x8x16"), (32, "8x4"), (2, "2"), (4096, "8x8x8x8")])
+def test_describe_factorisations(n, rad):
+    _, passes = parse_describe(croft.croft_plan_describe(n, 2, 3))
+    assert passes[0]["radices"] == rad and passes[0]["kernel"] == "static"
+
+
+def test_describe_generic_fallback_and_skipped_axes():
+    _, passes = parse_describe(croft.croft_plan_describe(45, 1, 27))
+    assert [p["axis"] for p in passes] == ["x", "z"]          # length-1 axis skipped
+    assert passes[0]["kernel"] == "generic" and passes[0]["radices"] == "5x3x3"
+    assert passes[1]["kind"] == "strided" and passes[1]["stride"] == "45"
+    _, passes = parse_describe(croft.croft_plan_describe(1, 1, 1))
+    assert len(passes) == 1 and passes[0]["radices"] == "copy"
+    _, passes = parse_describe(croft.croft_plan_describe(1, 30, 8))
+    assert passes[0]["axis"] == "y" and passes[0]["kind"] == "contiguous"
+
+
+def test_describe_half_runs_every_axis():
+    _, passes = parse_describe(croft.croft_plan_describe(1, 16, 1, croft.CROFT_C16F))
+    assert [p["axis"] for p in passes] == ["x", "y", "z"]
+    assert [p["n"] for p in passes] == ["1", "16", "1"]
+
+
+def test_describe_launch_shapes_fit_the_device():
+    for n in [2, 3, 5, 8, 16, 45, 48, 60, 100, 384, 512, 1000, 1024, 3000, 4096]:
+        for dt in range(4):
+            _, passes = parse_describe(croft.croft_plan_describe(n, 8, 16, dt))
+            for p in passes:
+                assert int(p["block"]) <= 1024 and int(p["block"]) % 1 == 0
+                assert int(p["lds"]) <= 160 * 1024
+                assert int(p["T"]) * int(p["L"]) <= int(p["block"])

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP path against the FP64 oracle on seeded inputs.
+
+Sizes here are ones the oracle finishes in seconds; they span several blocks
+and ragged tails, static and runtime-radix kernels, every dtype and both
+directions.  Full-size configurations are in test_gpu_fullsize.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2002_04896_amd as croft
+from paper_2002_04896_amd import synth
+from gpu_helpers import HALF_KIND, TOL, run_fft, run_half, to_device
+
+pytestmark = pytest.mark.gpu
+
+C64, C128, F16, BF16 = croft.CROFT_C64, croft.CROFT_C128, croft.CROFT_C16F, croft.CROFT_C16B
+FWD, BWD = croft.CROFT_FORWARD, croft.CROFT_BACKWARD
+
+
+def test_config_32cube_c64_uniform_forward_and_roundtrip():
+    # single forward 32^3 c64, Uniform[-1,1) re/im, seed 1; plus inverse round trip
+    x = synth.uniform_c((32, 32, 32), seed=1)
+    seen, y, _ = run_fft(x, C64, FWD)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, -1)) <= TOL[C64]
+    d = to_device(y, C64)
+    plan = croft.croft_plan_create(32, 32, 32, C64, BWD)
+    back = torch.empty_like(d)
+    croft.croft_execute(plan, d, back)
+    torch.cuda.synchronize()
+    croft.croft_plan_destroy(plan)
+    assert oracle.rel_l2(back.cpu().numpy() / x.size, seen) <= 1e-5
+
+
+def test_config_32cube_c128():
+    x = synth.uniform_c((32, 32, 32), seed=1)
+    seen, y, _ = run_fft(x, C128, FWD)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, -1)) <= TOL[C128]
+    seen, y, _ = run_fft(x, C128, BWD)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, +1)) <= TOL[C128]
+
+
+# (nz, ny, nx): non-cubic, ragged tiles, mixed radix, length-1 axes, runtime-radix lengths
+SHAPES = [(100, 60, 48), (48, 100, 60), (27, 45, 60), (3, 128, 5), (8, 30, 1), (1, 1, 1),
+          (1, 1, 8), (64, 1, 1), (80, 72, 96), (5, 3, 2), (16, 384, 12), (2, 7 * 0 + 6, 1000),
+          (12, 3, 1024), (9, 2048, 2), (2, 2, 4096), (25, 36, 40)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=str)
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+@pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
+def test_shapes_against_oracle(shape, dtype, direction):
+    x = synth.normal_c(shape, seed=2)
+    seen, y, after = run_fft(x, dtype, direction)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, direction)) <= TOL[dtype]
+    assert np.array_equal(after, seen)                      # out of place keeps the input
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_in_place_equals_out_of_place_bitwise(dtype):
+    x = synth.normal_c((40, 36, 50), seed=3)
+    _, y_oop, _ = run_fft(x, dtype)
+    _, y_ip, _ = run_fft(x, dtype, inplace=True)
+    assert np.array_equal(y_oop, y_ip)
+
+
+def test_repeat_runs_bitwise_identical():
+    x = synth.normal_c((64, 48, 60), seed=4)
+    runs = [run_fft(x, C64)[1] for _ in range(3)]
+    assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[1], runs[2])
+
+
+@pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
+def test_shifted_delta_closed_form(dtype):
+    # delta at an asymmetric point of a non-cubic grid -> full plane wave
+    nz, ny, nx = 20, 12, 30
+    az, ay, ax = 3, 7, 11
+    x = np.zeros((nz, ny, nx), complex)
+    x[az, ay, ax] = 1
+    _, y, _ = run_fft(x, dtype)
+    kz, ky, kx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    want = np.exp(-2j * np.pi * (kx * ax / nx + ky * ay / ny + kz * az / nz))
+    assert oracle.rel_l2(y, want) <= TOL[dtype]
+
+
+def test_constant_and_plane_wave_closed_forms():
+    x = np.full((24, 20, 16), 0.5 - 0.25j)
+    _, y, _ = run_fft(x, C64)
+    want = np.zeros_like(x)
+    want[0, 0, 0] = x.size * (0.5 - 0.25j)
+    assert oracle.rel_l2(y, want) <= 1e-6
+    jz, jy, jx = np.meshgrid(np.arange(24), np.arange(20), np.arange(16), indexing="ij")
+    x = np.exp(2j * np.pi * (3 * jx / 16 + 5 * jy / 20 + 7 * jz / 24))
+    _, y, _ = run_fft(x, C128)
+    want = np.zeros_like(x)
+    want[7, 5, 3] = x.size
+    assert oracle.rel_l2(y, want) <= 1e-12
+
+
+def test_generic_kernels_match_oracle_on_hot_lengths():
+    # the runtime-radix kernels, forced, on lengths that normally run static kernels
+    x = synth.normal_c((48, 60, 64), seed=5)
+    seen, y, _ = run_fft(x, C64, flags=croft.CROFT_FORCE_GENERIC)
+    assert oracle.rel_l2(y, oracle.dft3d(seen)) <= TOL[C64]
+    seen, y, _ = run_fft(x, C128, BWD, flags=croft.CROFT_FORCE_GENERIC)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, +1)) <= TOL[C128]
+
+
+@pytest.mark.parametrize("slabs", [2, 4, 8])
+def test_slab_schedule_is_bitwise_equal_to_plain(slabs):
+    x = synth.normal_c((64, 40, 48), seed=6)
+    _, plain, _ = run_fft(x, C64)
+    _, piped, _ = run_fft(x, C64, slabs=slabs)
+    assert np.array_equal(plain, piped)
+
+
+def check_half_output(out_bits, out_exp, kind):
+    """Every z-line's largest |re|, |im| was scaled into [2^14, 2^15) before
+    rounding (so it is in [2^14, 2^15] after), or the line is zero."""
+    parts = out_bits.view(np.float16).astype(np.float64) if kind == "f16" else \
+        (out_bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    peak = np.abs(parts).max(axis=(0, 3))                    # (ny, nx)
+    ok = ((peak >= 2.0 ** 14) & (peak <= 2.0 ** 15)) | ((peak == 0) & (out_exp == 0))
+    assert ok.all()
+
+
+@pytest.mark.parametrize("dtype", [F16, BF16], ids=["f16", "bf16"])
+@pytest.mark.parametrize("shape", [(40, 48, 64), (27, 60, 45), (1, 16, 1), (6, 1, 100)], ids=str)
+def test_half_storage_against_oracle(dtype, shape):
+    kind = HALF_KIND[dtype]
+    v = synth.normal_c(shape, seed=7)
+    data, e = synth.quantize_half(v, kind)
+    exact_in = oracle.decode_half(data, e, kind, 0)
+    for direction in (FWD, BWD):
+        out, oe = run_half(data, e, dtype, direction)
+        got = oracle.decode_half(out, oe, kind, 2)
+        assert oracle.rel_l2(got, oracle.dft3d(exact_in, direction)) <= TOL[dtype]
+        check_half_output(out, oe, kind)
+
+
+@pytest.mark.parametrize("dtype", [F16, BF16], ids=["f16", "bf16"])
+def test_half_in_place_slabs_and_null_exponents(dtype):
+    kind = HALF_KIND[dtype]
+    v = synth.normal_c((32, 24, 40), seed=8)
+    data, e = synth.quantize_half(v, kind)
+    ref_out, ref_e = run_half(data, e, dtype)
+    out, oe = run_half(data, e, dtype, inplace=True)
+    assert np.array_equal(out, ref_out) and np.array_equal(oe, ref_e)
+    out, oe = run_half(data, e, dtype, slabs=4)
+    assert np.array_equal(out, ref_out) and np.array_equal(oe, ref_e)
+    out, oe = run_half(data, np.zeros_like(e), dtype, in_exp_null=True)
+    got = oracle.decode_half(out, oe, kind, 2)
+    assert oracle.rel_l2(got, oracle.dft3d(oracle.decode_half(data, np.zeros_like(e), kind, 0))) <= 5e-3
+
+
+def test_half_all_zero_input():
+    data = np.zeros((8, 8, 8, 2), np.uint16)
+    out, oe = run_half(data, np.zeros((8, 8), np.int8), F16)
+    assert not out.any() and not oe.any()
+
+
+def test_batched_uneven_grids():
+    dims = [(48, 60, 64), (128, 72, 80), (100, 96, 48), (60, 60, 60), (8, 1, 3), (45, 27, 2)]
+    plan = croft.croft_plan_create_batched(dims, C64, FWD)
+    offs = croft.croft_plan_batched_offsets(plan, len(dims))
+    assert offs[0] == 0 and offs[-1] == sum(a * b * c for a, b, c in dims)
+    xs = [synth.pme_grid(nx, ny, nz, seed=10 + i)[0].astype(complex) for i, (nx, ny, nz) in enumerate(dims)]
+    flat = np.concatenate([x.ravel() for x in xs]).astype(np.complex64)
+    d_in = torch.from_numpy(flat).cuda()
+    d_out = torch.full_like(d_in, complex(float("nan"), 0))
+    for _ in range(2):                      # second call replays the captured graph
+        croft.croft_execute_batched(plan, d_in, d_out)
+    torch.cuda.synchronize()
+    croft.croft_plan_destroy(plan)
+    out = d_out.cpu().numpy()
+    for i, (nx, ny, nz) in enumerate(dims):
+        seen = flat[offs[i]:offs[i + 1]].reshape(nz, ny, nx).astype(np.complex128)
+        got = out[offs[i]:offs[i + 1]].reshape(nz, ny, nx)
+        assert oracle.rel_l2(got, oracle.dft3d(seen)) <= TOL[C64], f"grid {i} {dims[i]}"
+
+
+def test_profile_records_each_pass():
+    plan = croft.croft_plan_create(64, 64, 64, C64, FWD)
+    d = to_device(synth.normal_c((64, 64, 64), 9), C64)
+    out = torch.empty_like(d)
+    croft.croft_plan_profile(plan, True)
+    for _ in range(3):
+        croft.croft_execute(plan, d, out)
+    ms, n = croft.croft_plan_profile_read(plan)
+    croft.croft_plan_destroy(plan)
+    assert n == 3 and all(m > 0 for m in ms[:3]) and ms[3] == 0
+
+
+def test_execute_argument_errors_on_device():
+    plan = croft.croft_plan_create(16, 16, 16, C64, FWD)
+    d = torch.zeros((16, 16, 16), dtype=torch.complex64, device="cuda")
+    big = torch.zeros((2 * 16 * 16 * 16,), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError, match="overlap"):
+        croft.croft_execute(plan, big, big[1:])
+    with pytest.raises(ValueError, match="NULL"):
+        croft.croft_execute(plan, 0, d)
+    with pytest.raises(ValueError, match="scaled"):
+        croft.croft_execute_scaled(plan, d, None, d, torch.zeros(256, dtype=torch.int8, device="cuda"))
+    croft.croft_plan_destroy(plan)
+    hplan = croft.croft_plan_create(16, 16, 16, F16, FWD)
+    with pytest.raises(ValueError, match="half"):
+        croft.croft_execute(hplan, d, d)
+    with pytest.raises(ValueError, match="out_exp"):
+        croft.croft_execute_scaled(hplan, d, None, d, None)
+    croft.croft_plan_destroy(hplan)
