@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libcroft.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["croft_kernels.hip", "croft_plan.cpp", "croft_api.cpp"]
+SOURCES = ["croft_kernels.hip", "croft_plan.cpp", "croft_api.cpp", "croft_tune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
 # the device code must not use packed FP32 instructions
@@ -30,7 +30,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
     path = os.path.join(CSRC, src)
-    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    # kernels: no implicit contraction (their fused multiply-adds are explicit)
+    lang = ["-x", "hip", "-ffp-contract=off"] if src.endswith(".hip") else []
     cmd = [HIPCC, *COMMON, *DEVICE, *lang, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -12,6 +12,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "croft_internal.h"
@@ -115,8 +116,11 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
             p.nlines = p.es;
             p.nw = N / (p.es * n);
         }
-        if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, &p.cfg))
+        int cand = 0, waves = 1;
+        wisdom_lookup(n, p.kind, dtype, &cand, &waves);
+        if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
             return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+        p.cfg.grid_waves = waves;
         if (half) {
             ExpMap &m = p.em;
             const long long big = 1LL << 40;
@@ -146,7 +150,7 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
         p.es = 1;
         p.kind = kContiguous;
         p.nlines = 1;
-        if (!select_kernel(1, kContiguous, dtype, true, &p.cfg))
+        if (!select_kernel(1, kContiguous, dtype, true, 0, &p.cfg))
             return fail(CROFT_ERR_INTERNAL, "no kernel for a 1-point grid");
         out->push_back(p);
     }
@@ -206,6 +210,36 @@ void destroy_plan(croft_plan *p) {
     delete p;
 }
 
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+// Kernel attributes (LDS above 64 KiB) and the number of blocks the device
+// holds at once, which sizes the persistent grid.
+int prepare_kernel(KernelConfig *cfg) {
+    hipError_t e;
+    const void *fs[2] = {cfg->func, cfg->func_inv};
+    for (int i = 0; i < 2; ++i) {
+        if (cfg->lds > 65536) {
+            e = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg->lds);
+            if (e != hipSuccess) return fail_hip(e, "LDS attribute");
+        }
+    }
+    cfg->resident = 0;
+    if (!cfg->generic) {
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cfg->func, cfg->block, cfg->lds);
+        if (e != hipSuccess) return fail_hip(e, "occupancy query");
+        if (nb < 1) return fail(CROFT_ERR_INTERNAL, "kernel cannot be resident (block %d, LDS %zu)", cfg->block,
+                                cfg->lds);
+        cfg->resident = nb * device_cus();
+    }
+    return CROFT_SUCCESS;
+}
+
 // Device resources for the passes of every grid: twiddle tables (one per
 // distinct length), exponent scratch, kernel attributes.
 int attach_resources(croft_plan *p) {
@@ -234,11 +268,8 @@ int attach_resources(croft_plan *p) {
                 if (e != hipSuccess) return fail_hip(e, "twiddle upload");
             }
             pl.tw = pl.n > 1 ? p->twiddles[pl.n] : nullptr;
-            if (pl.cfg.lds > 65536) {
-                e = hipFuncSetAttribute(pl.cfg.func, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)pl.cfg.lds);
-                if (e != hipSuccess) return fail_hip(e, "LDS attribute");
-            }
+            const int rc = prepare_kernel(&pl.cfg);
+            if (rc != CROFT_SUCCESS) return rc;
         }
     }
     if (is_half(p->dtype)) {
@@ -260,6 +291,91 @@ int attach_resources(croft_plan *p) {
         if ((e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess)
             return fail_hip(e, "event create");
     }
+    return CROFT_SUCCESS;
+}
+
+// CROFT_MEASURE: time every compiled configuration of each distinct pass
+// (candidate x persistent grid size) on scratch buffers, keep the fastest and
+// record it as wisdom.
+int measure_passes(croft_plan *p) {
+    size_t maxN = 0, maxE = 1;
+    for (const Geometry &g : p->grids) {
+        maxN = std::max(maxN, (size_t)g.nx * g.ny * g.nz);
+        maxE = std::max({maxE, (size_t)g.ny * g.nz, (size_t)g.nx * g.nz, (size_t)g.nx * g.ny});
+    }
+    const size_t bytes = maxN * element_bytes(p->dtype);
+    void *a = nullptr, *b = nullptr;
+    int8_t *ei = nullptr, *eo = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int rc = CROFT_SUCCESS;
+    auto cleanup = [&]() {
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (ei) (void)hipFree(ei);
+        if (eo) (void)hipFree(eo);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    };
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess ||
+        hipMalloc((void **)&ei, maxE) != hipSuccess || hipMalloc((void **)&eo, maxE) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(CROFT_ERR_OUT_OF_MEMORY, "autotune scratch of %zu bytes", 2 * bytes);
+    }
+    hipError_t e;
+    if ((e = hipMemset(a, 0, bytes)) != hipSuccess || (e = hipMemset(ei, 0, maxE)) != hipSuccess ||
+        (e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "autotune setup");
+    }
+    const bool persist = !(p->flags & CROFT_NO_WISDOM);
+    const bool inv = p->dir == CROFT_BACKWARD;
+    std::map<std::tuple<int, int>, KernelConfig> best;  // (n, kind) -> configuration
+    for (auto &ps : p->passes) {
+        for (PassLaunch &pl : ps) {
+            if (pl.cfg.generic || best.count({pl.n, pl.kind})) continue;
+            const int ncand = kernel_candidates(pl.n, pl.kind, p->dtype);
+            float best_ms = 1e30f;
+            KernelConfig pick = pl.cfg;
+            for (int c = 0; c < ncand && rc == CROFT_SUCCESS; ++c) {
+                KernelConfig cfg;
+                if (!select_kernel(pl.n, pl.kind, p->dtype, false, c, &cfg) || cfg.candidate != c) continue;
+                if ((rc = prepare_kernel(&cfg)) != CROFT_SUCCESS) break;
+                for (int waves : {1, 2, 0}) {
+                    PassLaunch t = pl;
+                    t.cfg = cfg;
+                    t.cfg.grid_waves = waves;
+                    float ms = 0.f;
+                    for (int rep = 0; rep < 2 && (e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0)) == hipSuccess;
+                         ++rep) {
+                    }
+                    if (e == hipSuccess) e = hipEventRecord(t0, 0);
+                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0);
+                    if (e == hipSuccess) e = hipEventRecord(t1, 0);
+                    if (e == hipSuccess) e = hipEventSynchronize(t1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                    if (e != hipSuccess) {
+                        rc = fail_hip(e, "autotune launch");
+                        break;
+                    }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        pick = t.cfg;
+                    }
+                }
+            }
+            if (rc != CROFT_SUCCESS) break;
+            best[{pl.n, pl.kind}] = pick;
+            wisdom_record(pl.n, pl.kind, p->dtype, pick.candidate, pick.grid_waves, persist);
+        }
+    }
+    cleanup();
+    if (rc != CROFT_SUCCESS) return rc;
+    for (auto &ps : p->passes)
+        for (PassLaunch &pl : ps) {
+            auto it = best.find({pl.n, pl.kind});
+            if (it != best.end()) pl.cfg = it->second;
+        }
     return CROFT_SUCCESS;
 }
 
@@ -293,7 +409,7 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
         delete p;
         return nullptr;
     }
-    if (attach_resources(p) != CROFT_SUCCESS) {
+    if (attach_resources(p) != CROFT_SUCCESS || ((flags & CROFT_MEASURE) && measure_passes(p) != CROFT_SUCCESS)) {
         std::string msg = g_last_error;
         destroy_plan(p);
         g_last_error = msg;
@@ -651,11 +767,11 @@ int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, s
                                                         : ((pl.es + pl.cfg.lines - 1) / pl.cfg.lines) * pl.nw;
         snprintf(line, sizeof line,
                  "pass %zu axis=%c n=%d kind=%s kernel=%s radices=%s stride=%lld lines=%lld T=%d L=%d block=%d "
-                 "blocks=%lld lds=%zu\n",
+                 "blocks=%lld lds=%zu candidate=%d waves=%d\n",
                  i, "xyz"[pl.axis], pl.n, pl.kind == kContiguous ? "contiguous" : "strided",
                  pl.cfg.generic ? "generic" : "static", rad.c_str(), pl.es,
                  pl.kind == kContiguous ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
-                 pl.cfg.block, blocks, pl.cfg.lds);
+                 pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves);
         s += line;
     }
     if (len) {

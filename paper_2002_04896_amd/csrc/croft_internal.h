@@ -29,14 +29,19 @@ inline size_t element_bytes(int dtype) {
 //                         w < nw; consecutive p are adjacent in memory and a
 //                         block takes a tile of `lines` consecutive p.
 struct KernelConfig {
-    const void *func = nullptr;  // the __global__ function
-    bool generic = false;        // runtime-radix kernel
-    int threads_per_line = 0;    // T
-    int lines = 0;               // L, lines per block
-    int block = 0;               // T * L
-    size_t lds = 0;              // dynamic LDS bytes per block
+    const void *func = nullptr;      // the __global__ function (forward)
+    const void *func_inv = nullptr;  // the same configuration, inverse direction
+    bool generic = false;            // runtime-radix kernel
+    int candidate = 0;               // index among the compiled configurations
+    int threads_per_line = 0;        // T
+    int lines = 0;                   // L, lines per block
+    int block = 0;                   // T * L
+    size_t lds = 0;                  // dynamic LDS bytes per block
     int nstages = 0;
     int radix[kMaxStages] = {};
+    int resident = 0;    // blocks the device holds at once (0: unknown)
+    int grid_waves = 1;  // static kernels: launch min(tiles, resident * grid_waves)
+                         // blocks looping over tiles; 0 launches one block per tile
 };
 
 // Exponent addressing of the half-storage form.  For an element at line
@@ -68,14 +73,22 @@ struct Geometry {
 };
 
 // ---- kernels (croft_kernels.hip) ----
-// Look up the compiled configuration for a pass; generic == true falls back
-// to the runtime-radix kernel.  Returns false if no kernel can run it.
-bool select_kernel(int n, int kind, int dtype, bool force_generic, KernelConfig *cfg);
-
+// Number of compiled static configurations for (n, kind, dtype).
+int kernel_candidates(int n, int kind, int dtype);
+// Look up compiled configuration `cand` (0 = default; an unknown index falls
+// back to 0) for a pass; with force_generic, or when no static kernel exists,
+// the runtime-radix kernel.  Returns false if no kernel can run it.
+bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, KernelConfig *cfg);
+// Tiles (blocks of work) of one launch of a pass.
+long long pass_tiles(const PassLaunch &pl);
 // Launch one pass.  `in`/`out` point at the first element of the lines the
 // launch covers; exponent pointers likewise (half storage only).
 hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *out,
                        const int8_t *in_exp, int8_t *out_exp, int inverse, hipStream_t stream);
+
+// ---- wisdom (croft_tune.cpp) ----
+bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves);
+void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist);
 
 // ---- planner (croft_plan.cpp) ----
 bool smooth_length(int n);

@@ -28,6 +28,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "croft_internal.h"
 
 namespace croft {
@@ -42,9 +44,18 @@ template <typename R>
 __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename R>
 __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+// Floating-point contraction is off for this file (-ffp-contract=off): every
+// fused multiply-add below is written out, so the rounding of each operation
+// is fixed by the source and does not depend on how a configuration is
+// scheduled -- all tile shapes of a length give bit-identical results.
+template <typename R>
+__device__ __forceinline__ R fmaR(R a, R b, R c) {
+    return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {fmaR(a.x, b.x, -(a.y * b.y)), fmaR(a.x, b.y, a.y * b.x)};
 }
 template <typename R>
 __device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.x * s, a.y * s}; }
@@ -91,11 +102,11 @@ template <typename R>
 struct Dft<3, R> {
     static __device__ __forceinline__ void run(cx<R> *v) {
         const cx<R> t = v[1] + v[2], d = v[1] - v[2];
-        const cx<R> m = {v[0].x - R(0.5) * t.x, v[0].y - R(0.5) * t.y};
+        const cx<R> m = {fmaR(R(-0.5), t.x, v[0].x), fmaR(R(-0.5), t.y, v[0].y)};
         const R s = Kc<R>::s3;
         v[0] = v[0] + t;
-        v[1] = {m.x + s * d.y, m.y - s * d.x};
-        v[2] = {m.x - s * d.y, m.y + s * d.x};
+        v[1] = {fmaR(s, d.y, m.x), fmaR(-s, d.x, m.y)};
+        v[2] = {fmaR(-s, d.y, m.x), fmaR(s, d.x, m.y)};
     }
 };
 
@@ -109,10 +120,12 @@ struct Dft<5, R> {
     static __device__ __forceinline__ void run(cx<R> *v) {
         using K = Kc<R>;
         const cx<R> t1 = v[1] + v[4], t2 = v[2] + v[3], d1 = v[1] - v[4], d2 = v[2] - v[3];
-        const cx<R> m1 = {v[0].x + K::c51 * t1.x + K::c52 * t2.x, v[0].y + K::c51 * t1.y + K::c52 * t2.y};
-        const cx<R> m2 = {v[0].x + K::c52 * t1.x + K::c51 * t2.x, v[0].y + K::c52 * t1.y + K::c51 * t2.y};
-        const cx<R> n1 = {K::s51 * d1.x + K::s52 * d2.x, K::s51 * d1.y + K::s52 * d2.y};
-        const cx<R> n2 = {K::s52 * d1.x - K::s51 * d2.x, K::s52 * d1.y - K::s51 * d2.y};
+        const cx<R> m1 = {fmaR(K::c52, t2.x, fmaR(K::c51, t1.x, v[0].x)),
+                          fmaR(K::c52, t2.y, fmaR(K::c51, t1.y, v[0].y))};
+        const cx<R> m2 = {fmaR(K::c51, t2.x, fmaR(K::c52, t1.x, v[0].x)),
+                          fmaR(K::c51, t2.y, fmaR(K::c52, t1.y, v[0].y))};
+        const cx<R> n1 = {fmaR(K::s52, d2.x, K::s51 * d1.x), fmaR(K::s52, d2.y, K::s51 * d1.y)};
+        const cx<R> n2 = {fmaR(-K::s51, d2.x, K::s52 * d1.x), fmaR(-K::s51, d2.y, K::s52 * d1.y)};
         v[0] = v[0] + t1 + t2;
         v[1] = {m1.x + n1.y, m1.y - n1.x};
         v[4] = {m1.x - n1.y, m1.y + n1.x};
@@ -174,13 +187,16 @@ struct Dft<16, R> {
 };
 
 // ------------------------------------------------------- storage policies
+// fetch() issues the global load and returns the stored bits untouched, so a
+// prefetched tile costs no arithmetic until decode() runs on it.
 struct StC64 {
     using R = float;
+    using Raw = float2;
     static constexpr bool kHalf = false;
-    static __device__ __forceinline__ cx<R> load(const void *p, long long i, int) {
-        const float2 v = reinterpret_cast<const float2 *>(p)[i];
-        return {v.x, v.y};
+    static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
+        return reinterpret_cast<const float2 *>(p)[i];
     }
+    static __device__ __forceinline__ cx<R> decode(Raw r, int) { return {r.x, r.y}; }
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int) {
         reinterpret_cast<float2 *>(p)[i] = make_float2(v.x, v.y);
     }
@@ -188,11 +204,12 @@ struct StC64 {
 
 struct StC128 {
     using R = double;
+    using Raw = double2;
     static constexpr bool kHalf = false;
-    static __device__ __forceinline__ cx<R> load(const void *p, long long i, int) {
-        const double2 v = reinterpret_cast<const double2 *>(p)[i];
-        return {v.x, v.y};
+    static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
+        return reinterpret_cast<const double2 *>(p)[i];
     }
+    static __device__ __forceinline__ cx<R> decode(Raw r, int) { return {r.x, r.y}; }
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int) {
         reinterpret_cast<double2 *>(p)[i] = make_double2(v.x, v.y);
     }
@@ -217,10 +234,13 @@ __device__ __forceinline__ unsigned short float_to_bf16_bits(float f) {
 template <bool BF>
 struct StHalf {
     using R = float;
+    using Raw = unsigned;
     static constexpr bool kHalf = true;
+    static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
+        return reinterpret_cast<const unsigned *>(p)[i];
+    }
     // value = stored * 2^e
-    static __device__ __forceinline__ cx<R> load(const void *p, long long i, int e) {
-        const unsigned u = reinterpret_cast<const unsigned *>(p)[i];
+    static __device__ __forceinline__ cx<R> decode(Raw u, int e) {
         const unsigned short lo = static_cast<unsigned short>(u & 0xffffu);
         const unsigned short hi = static_cast<unsigned short>(u >> 16);
         const float re = BF ? bf16_bits_to_float(lo) : f16_bits_to_float(lo);
@@ -243,8 +263,15 @@ __device__ __forceinline__ int line_exponent(float mx) {
     if (!(mx <= 3.402823466e38f)) return 127;
     int E;
     frexpf(mx, &E);  // mx = f 2^E, f in [0.5, 1)
-    int e = E - 15;
+    const int e = E - 15;
     return e < -128 ? -128 : (e > 127 ? 127 : e);
+}
+
+// The inverse transform is swap(DFT(swap(x))) with swap(a + ib) = b + ia.
+template <bool INV, typename R>
+__device__ __forceinline__ cx<R> maybe_swap(cx<R> v) {
+    if constexpr (INV) return {v.y, v.x};
+    return v;
 }
 
 // --------------------------------------------------------- launch arguments
@@ -258,8 +285,9 @@ struct PassArgs {
     long long es;      // element stride
     long long nw;      // strided: w count
     long long ntiles;  // strided: tiles of L lines per w
+    long long total;   // tiles in the launch
     ExpMap em;
-    int inverse;
+    int inverse;       // runtime-radix kernel only (static kernels take it as a template argument)
     // runtime-radix kernel only
     int n, T, L, S;
     int radix[kMaxStages];
@@ -302,6 +330,13 @@ constexpr int ns_before(const RPlan &p, int s) {
     for (int i = 0; i < s; ++i) v *= p.r[i];
     return v;
 }
+// LDS twiddle table: stage s >= 1 holds (r_s - 1) * Ns_s entries,
+// entry (q, k) = w_N^(q k N / (Ns R)) at offset (q - 1) Ns + k.
+constexpr int tw_offset(const RPlan &p, int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += (p.r[i] - 1) * ns_before(p, i);
+    return o;
+}
 
 constexpr int floor_pow2(int v) {
     int p = 1;
@@ -311,90 +346,176 @@ constexpr int floor_pow2(int v) {
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-constexpr int kLdsLimit = 65536;
+// LDS budget used to size default tiles: two blocks fit in a CU's 160 KiB.
+constexpr int kLdsLimit = 80 * 1024;
 
-// Compile-time launch shape of the static kernel for length N.
-// T = N / rmax threads per line (one butterfly per thread on the largest-radix
-// stages).  Contiguous passes take about 256 threads per block.  Strided
-// passes take L neighbouring lines so that each row of the tile is a
-// 128-byte segment (16 x 8-byte, 8 x 16-byte or 32 x 4-byte elements), or
-// more lines when T is small, within 1024 threads and the LDS limit.
-template <int N, int KIND, int STORE_BYTES, int COMPUTE_BYTES>
+// Compile-time launch shape of a static kernel for length N.
+//   EPT: elements per thread (T = N / EPT threads per line); 0 = the largest
+//        radix, so the largest-radix stages take one butterfly per thread.
+//   LREQ: lines per block; 0 = the default: about 256 threads for contiguous
+//        lines; for strided lines enough neighbouring lines that each row of
+//        the tile is a 128-byte segment, more when T is small, within 1024
+//        threads and the LDS budget.
+//   PAD: contiguous lines only: one padding element per 32 in LDS.
+//   PF: prefetch the next tile's loads while transforming the current one.
+template <int N, int KIND, int STORE_BYTES, int COMPUTE_BYTES, int EPT = 0, int LREQ = 0, int PAD = 0,
+          int PF = 1>
 struct SCfg {
+    static constexpr bool kPrefetch = PF != 0;
     static constexpr RPlan plan = make_rplan(N);
     static constexpr int S = plan.S;
-    static constexpr int T = N / plan.rmax;
-    static constexpr int kLdsLines = cmax(1, kLdsLimit / (N * COMPUTE_BYTES));
-    static constexpr int L = KIND == kContiguous
+    static constexpr int kEpt = EPT > 0 ? EPT : plan.rmax;
+    static constexpr int T = cmax(1, N / kEpt);
+    static constexpr int kLineStride = (KIND == kContiguous && PAD) ? N + (N + 31) / 32 : N;
+    static constexpr int kTwN = tw_offset(plan, S);
+    static constexpr int kLdsLines = cmax(1, (kLdsLimit - kTwN * COMPUTE_BYTES) / (kLineStride * COMPUTE_BYTES));
+    static constexpr int L = LREQ > 0 ? LREQ
+                             : KIND == kContiguous
                                  ? floor_pow2(cmax(1, cmin(cmin(256 / T, 256), kLdsLines)))
                                  : floor_pow2(cmax(1, cmin(cmin(cmax(128 / STORE_BYTES, 256 / T), 1024 / T), kLdsLines)));
     static constexpr int kBlock = T * L;
-    static constexpr size_t kLds = (size_t)L * N * COMPUTE_BYTES + 4 * (size_t)L;
+    // lines never straddle a wavefront: stages sync per wave, not per block
+    static constexpr bool kWaveSync = KIND == kContiguous && T <= 64 && (64 % T) == 0;
+    static constexpr size_t kLdsData = (size_t)L * kLineStride * COMPUTE_BYTES;
+    static constexpr size_t kLds = kLdsData + (size_t)kTwN * COMPUTE_BYTES + 4 * (size_t)L;
 };
 
-// ------------------------------------------------------------ block context
-template <typename R>
-struct Ctx {
-    cx<R> *lds;
-    unsigned *red;     // per-line max (half storage)
-    long long base;    // element index of the line's first element
-    long long es;
-    int t, l, L, n;
-    bool valid;        // the line exists
-    int ebase;         // input exponent index without the j term
-    long long ea3;     // input exponent stride along the line
-    int kind;
-};
-
-template <int KIND>
-__device__ __forceinline__ int lds_index(int l, int e, int n, int L) {
-    return KIND == kContiguous ? l * n + e : e * L + l;
+template <int KIND, int LS, int PAD>
+__device__ __forceinline__ int lds_index(int l, int e, int L) {
+    if constexpr (KIND == kContiguous) return l * LS + e + (PAD ? (e >> 5) : 0);
+    return e * L + l;
 }
 
-template <class St>
-__device__ __forceinline__ cx<typename St::R> load_elem(const PassArgs &a, long long base, long long es,
-                                                        int e, int ebase, long long ea3) {
-    int ex = 0;
-    if (St::kHalf && a.in_exp) ex = a.in_exp[ebase + ea3 * e];
-    cx<typename St::R> v = St::load(a.in, base + es * e, ex);
-    if (a.inverse) v.y = -v.y;
-    return v;
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (WAVE) {
+        // all lanes of a line are in this wavefront: order its LDS accesses
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------ static kernel
-template <class Cfg, class St, int KIND, int S>
-__device__ __forceinline__ void static_stage(const PassArgs &a, Ctx<typename St::R> &c) {
+// A block holds a tile of L lines and loops over tiles with a stride of the
+// grid size; while one tile is transformed the global loads of the next are
+// in flight (they are only decoded when that tile starts).
+template <class Cfg, class St>
+struct Tile {
+    static constexpr int R0 = Cfg::plan.r[0];
+    static constexpr int NB0 = Cfg::plan.n / R0;
+    static constexpr int B0 = (NB0 + Cfg::T - 1) / Cfg::T;
+    typename St::Raw raw[B0][R0];
+    int ex[B0][R0];
+};
+
+struct TileCoord {
+    long long q;      // line coordinate of this thread (contiguous: line; strided: p)
+    long long w;      // strided: line block
+    long long tbase;  // element index of the tile's first element (uniform in the block)
+    bool valid;
+};
+
+// Element index = tbase + lane + (b T + q NB) es: the tile origin and the
+// stage offsets are uniform across the block, the lane part is fixed per
+// thread, so each access costs one address add.
+template <class Cfg, int KIND>
+__device__ __forceinline__ TileCoord tile_coord(const PassArgs &a, long long tx, long long w, int l) {
+    TileCoord c;
+    c.q = tx * Cfg::L + l;
+    c.w = w;
+    c.tbase = KIND == kContiguous ? tx * Cfg::L * Cfg::plan.n : tx * Cfg::L + w * a.es * Cfg::plan.n;
+    c.valid = c.q < (KIND == kContiguous ? a.nlines : a.es);
+    return c;
+}
+
+// Byte offset of the thread's first element from the tile origin; it fits in
+// 32 bits (the planner sends larger strides to the runtime-radix kernel), so
+// an access is a uniform 64-bit base plus this one per-thread register.
+template <class Cfg, class St, int KIND>
+__device__ __forceinline__ unsigned lane_offset(int l, int t, long long es) {
+    const long long e = (KIND == kContiguous ? (long long)l * Cfg::plan.n : (long long)l) + (long long)t * es;
+    return (unsigned)(e * (long long)sizeof(typename St::Raw));
+}
+
+template <class St>
+__device__ __forceinline__ typename St::Raw fetch_at(const void *p, long long uniform_elem, unsigned lane_bytes) {
+    const char *b = reinterpret_cast<const char *>(p) + uniform_elem * (long long)sizeof(typename St::Raw);
+    return *reinterpret_cast<const typename St::Raw *>(b + lane_bytes);
+}
+
+template <class St>
+__device__ __forceinline__ void store_at(void *p, long long uniform_elem, unsigned lane_bytes,
+                                         cx<typename St::R> v, int ex) {
+    char *b = reinterpret_cast<char *>(p) + uniform_elem * (long long)sizeof(typename St::Raw);
+    St::store(b + lane_bytes, 0, v, ex);
+}
+
+template <class Cfg, class St, int KIND>
+__device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c, int t, unsigned lane,
+                                           long long es, Tile<Cfg, St> &tl) {
+    using TL = Tile<Cfg, St>;
+    if (!c.valid) return;
+    int ebase = 0;
+    long long ea3 = 0;
+    if constexpr (St::kHalf) {
+        const ExpMap &m = a.em;
+        ebase = (int)((c.q % m.qmod) * m.a0 + (c.q / m.qmod) * m.a1 + c.w * m.a2);
+        ea3 = m.a3;
+    }
+#pragma unroll
+    for (int b = 0; b < TL::B0; ++b) {
+        const int j = t + b * Cfg::T;
+        if ((TL::NB0 % Cfg::T) == 0 || j < TL::NB0) {
+#pragma unroll
+            for (int q = 0; q < TL::R0; ++q) {
+                const long long u = c.tbase + (long long)(b * Cfg::T + q * TL::NB0) * es;
+                tl.raw[b][q] = fetch_at<St>(a.in, u, lane);
+                if constexpr (St::kHalf)
+                    tl.ex[b][q] = a.in_exp ? (int)a.in_exp[ebase + ea3 * (j + q * TL::NB0)] : 0;
+            }
+        }
+    }
+}
+
+template <class Cfg, class St, int KIND, bool INV, int S>
+__device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::R> *lds,
+                                             const cx<typename St::R> *tws, unsigned *red, int t, int l,
+                                             const TileCoord &c, unsigned lane, long long es,
+                                             const Tile<Cfg, St> &tl, int &ex_out) {
     using R = typename St::R;
     constexpr int N = Cfg::plan.n;
     constexpr int T = Cfg::T;
     constexpr int L = Cfg::L;
+    constexpr int LS = Cfg::kLineStride;
+    constexpr int PAD = LS != N;
     constexpr int RAD = Cfg::plan.r[S];
     constexpr int Ns = ns_before(Cfg::plan, S);
     constexpr int NB = N / RAD;
     constexpr int B = (NB + T - 1) / T;
     constexpr bool kGuard = (NB % T) != 0;
-    constexpr int kTwStride = N / (Ns * RAD);
     constexpr bool kLast = (S == Cfg::S - 1);
-    const cx<R> *tw = reinterpret_cast<const cx<R> *>(a.tw);
+    constexpr int kTw = tw_offset(Cfg::plan, S);
 
     cx<R> v[B][RAD];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const int j = c.t + b * T;
+        const int j = t + b * T;
         if (!kGuard || j < NB) {
 #pragma unroll
             for (int q = 0; q < RAD; ++q) {
-                const int e = j + q * NB;
                 if constexpr (S == 0) {
-                    v[b][q] = c.valid ? load_elem<St>(a, c.base, c.es, e, c.ebase, c.ea3) : cx<R>{R(0), R(0)};
+                    v[b][q] = maybe_swap<INV>(St::decode(tl.raw[b][q], St::kHalf ? tl.ex[b][q] : 0));
                 } else {
-                    v[b][q] = c.lds[lds_index<KIND>(c.l, e, N, L)];
+                    v[b][q] = lds[lds_index<KIND, LS, PAD>(l, j + q * NB, L)];
                 }
             }
             if constexpr (Ns > 1) {
                 const int k = j % Ns;
 #pragma unroll
-                for (int q = 1; q < RAD; ++q) v[b][q] = cmul(v[b][q], tw[q * k * kTwStride]);
+                for (int q = 1; q < RAD; ++q) v[b][q] = cmul(v[b][q], tws[kTw + (q - 1) * Ns + k]);
             }
             Dft<RAD, R>::run(v[b]);
         }
@@ -407,111 +528,150 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, Ctx<typename St:
             float mx = 0.0f;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int j = c.t + b * T;
+                const int j = t + b * T;
                 if (!kGuard || j < NB) {
 #pragma unroll
-                    for (int q = 0; q < RAD; ++q)
-                        mx = fmaxf(mx, fmaxf(fabsf(v[b][q].x), fabsf(v[b][q].y)));
+                    for (int q = 0; q < RAD; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[b][q].x), fabsf(v[b][q].y)));
                 }
             }
-            atomicMax(&c.red[c.l], __float_as_uint(mx));
-            __syncthreads();
-            ex = line_exponent(__uint_as_float(c.red[c.l]));
+            atomicMax(&red[l], __float_as_uint(mx));
+            stage_sync<Cfg::kWaveSync>();
+            ex = line_exponent(__uint_as_float(red[l]));
+            ex_out = ex;
         }
         if (c.valid) {
 #pragma unroll
             for (int b = 0; b < B; ++b) {
-                const int j = c.t + b * T;
+                const int j = t + b * T;
                 if (!kGuard || j < NB) {
 #pragma unroll
                     for (int q = 0; q < RAD; ++q) {
-                        cx<R> o = v[b][q];
-                        if (a.inverse) o.y = -o.y;
-                        St::store(a.out, c.base + c.es * (j + q * NB), o, ex);
+                        const long long u = c.tbase + (long long)(b * T + q * NB) * es;
+                        store_at<St>(a.out, u, lane, maybe_swap<INV>(v[b][q]), ex);
                     }
                 }
             }
         }
-        if constexpr (St::kHalf) c.ebase = ex;  // hand the exponent back to the caller
     } else {
-        if constexpr (S > 0) __syncthreads();
+        if constexpr (S > 0) stage_sync<Cfg::kWaveSync>();
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int j = c.t + b * T;
+            const int j = t + b * T;
             if (!kGuard || j < NB) {
                 const int k = j % Ns;
                 const int o0 = (j / Ns) * Ns * RAD + k;
 #pragma unroll
-                for (int q = 0; q < RAD; ++q) c.lds[lds_index<KIND>(c.l, o0 + q * Ns, N, L)] = v[b][q];
+                for (int q = 0; q < RAD; ++q) lds[lds_index<KIND, LS, PAD>(l, o0 + q * Ns, L)] = v[b][q];
             }
         }
-        __syncthreads();
-        static_stage<Cfg, St, KIND, S + 1>(a, c);
+        stage_sync<Cfg::kWaveSync>();
+        static_stage<Cfg, St, KIND, INV, S + 1>(a, lds, tws, red, t, l, c, lane, es, tl, ex_out);
     }
 }
 
-// Line coordinates of this thread: contiguous q = line; strided q = p, w.
-template <int KIND>
-__device__ __forceinline__ void line_coords(const PassArgs &a, int l, int L, long long &q, long long &w,
-                                            bool &valid) {
-    if (KIND == kContiguous) {
-        q = (long long)blockIdx.x * L + l;
-        w = 0;
-        valid = q < a.nlines;
-    } else {
-        const long long tile = (long long)blockIdx.x % a.ntiles;
-        w = (long long)blockIdx.x / a.ntiles;
-        q = tile * L + l;
-        valid = q < a.es;
+template <class Cfg>
+__device__ __forceinline__ int tw_source(int i) {
+    // entry i of the LDS twiddle table -> index into the length-N table
+    constexpr RPlan p = Cfg::plan;
+    int src = 0;
+#pragma unroll
+    for (int s = 1; s < kMaxStages; ++s) {
+        if (s < p.S) {
+            const int o = tw_offset(p, s), ns = ns_before(p, s), r = p.r[s];
+            if (i >= o && i < o + (r - 1) * ns) {
+                const int q = (i - o) / ns + 1, k = (i - o) % ns;
+                src = q * k * (p.n / (ns * r));
+            }
+        }
     }
+    return src;
 }
 
-template <class Cfg, class St, int KIND>
+template <class Cfg, class St, int KIND, bool INV>
 __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
     using R = typename St::R;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int N = Cfg::plan.n;
     constexpr int T = Cfg::T;
     constexpr int L = Cfg::L;
-    Ctx<R> c;
-    c.lds = reinterpret_cast<cx<R> *>(smem);
-    c.red = reinterpret_cast<unsigned *>(smem + (size_t)L * N * sizeof(cx<R>));
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
+    unsigned *red = reinterpret_cast<unsigned *>(smem + Cfg::kLdsData + (size_t)Cfg::kTwN * sizeof(cx<R>));
     const int tid = threadIdx.x;
-    if (KIND == kContiguous) {
-        c.l = tid / T;
-        c.t = tid % T;
-    } else {
-        c.l = tid % L;
-        c.t = tid / L;
-    }
-    long long q, w;
-    line_coords<KIND>(a, c.l, L, q, w, c.valid);
-    c.es = KIND == kContiguous ? 1 : a.es;
-    c.base = KIND == kContiguous ? q * N : q + w * a.es * N;
-    c.L = L;
-    c.n = N;
-    c.kind = KIND;
-    c.ebase = 0;
-    c.ea3 = 0;
-    if constexpr (St::kHalf) {
-        const ExpMap &m = a.em;
-        c.ebase = (int)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2);
-        c.ea3 = m.a3;
-        if (c.t == 0) c.red[c.l] = 0u;
+    const int l = KIND == kContiguous ? tid / T : tid % L;
+    const int t = KIND == kContiguous ? tid % T : tid / L;
+
+    if constexpr (Cfg::kTwN > 0) {
+        const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
+        for (int i = tid; i < Cfg::kTwN; i += Cfg::kBlock) tws[i] = W[tw_source<Cfg>(i)];
         __syncthreads();
     }
-    static_stage<Cfg, St, KIND, 0>(a, c);
-    if constexpr (St::kHalf) {
-        if (c.valid && c.t == 0 && a.out_exp) {
-            const ExpMap &m = a.em;
-            a.out_exp[(q % m.qmod) * m.b0 + (q / m.qmod) * m.b1 + w * m.b2] = (int8_t)c.ebase;
+
+    long long tile = blockIdx.x;
+    if (tile >= a.total) return;
+    const long long G = gridDim.x;
+    const long long es = KIND == kContiguous ? 1 : a.es;
+    // tile -> (tx, w), advanced incrementally by G tiles per iteration
+    long long tx, w, gx = G, gw = 0;
+    if constexpr (KIND == kContiguous) {
+        tx = tile;
+        w = 0;
+    } else {
+        tx = tile % a.ntiles;
+        w = tile / a.ntiles;
+        gx = G % a.ntiles;
+        gw = G / a.ntiles;
+    }
+    Tile<Cfg, St> cur;
+    TileCoord c = tile_coord<Cfg, KIND>(a, tx, w, l);
+    const unsigned lane = lane_offset<Cfg, St, KIND>(l, t, es);
+    if constexpr (Cfg::kPrefetch) fetch_tile<Cfg, St, KIND>(a, c, t, lane, es, cur);
+    for (;;) {
+        const long long nt = tile + G;
+        const bool more = nt < a.total;
+        long long ntx = tx + gx, nw = w + gw;
+        if (KIND != kContiguous && ntx >= a.ntiles) {
+            ntx -= a.ntiles;
+            nw += 1;
         }
+        const TileCoord nc = tile_coord<Cfg, KIND>(a, ntx, nw, l);
+        Tile<Cfg, St> nxt;
+        if constexpr (Cfg::kPrefetch) {
+            if (more) fetch_tile<Cfg, St, KIND>(a, nc, t, lane, es, nxt);
+        } else {
+            fetch_tile<Cfg, St, KIND>(a, c, t, lane, es, cur);
+        }
+
+        int ex = 0;
+        if constexpr (St::kHalf) {
+            if (t == 0) red[l] = 0u;
+            stage_sync<Cfg::kWaveSync>();
+        }
+        static_stage<Cfg, St, KIND, INV, 0>(a, lds, tws, red, t, l, c, lane, es, cur, ex);
+        if constexpr (St::kHalf) {
+            if (c.valid && t == 0 && a.out_exp) {
+                const ExpMap &m = a.em;
+                a.out_exp[(c.q % m.qmod) * m.b0 + (c.q / m.qmod) * m.b1 + c.w * m.b2] = (int8_t)ex;
+            }
+        }
+        if (!more) break;
+        // the next tile overwrites LDS that this one read last
+        stage_sync<Cfg::kWaveSync>();
+        if constexpr (Cfg::kPrefetch) cur = nxt;
+        c = nc;
+        tile = nt;
+        tx = ntx;
+        w = nw;
     }
 }
 
 // ------------------------------------------------------- runtime-radix kernel
 // Any supported length.  Stages ping-pong between two LDS buffers, the last
 // stage included; a final sweep stores the line from LDS.
+template <int KIND>
+__device__ __forceinline__ int glds(int l, int e, int n, int L) {
+    return KIND == kContiguous ? l * n + e : e * L + l;
+}
+
 template <int RAD, typename R, int KIND>
 __device__ __forceinline__ void generic_stage(const cx<R> *src, cx<R> *dst, const cx<R> *tw, int n, int L,
                                               int l, int t, int T, int Ns) {
@@ -520,7 +680,7 @@ __device__ __forceinline__ void generic_stage(const cx<R> *src, cx<R> *dst, cons
     for (int j = t; j < NB; j += T) {
         cx<R> v[RAD];
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) v[q] = src[lds_index<KIND>(l, j + q * NB, n, L)];
+        for (int q = 0; q < RAD; ++q) v[q] = src[glds<KIND>(l, j + q * NB, n, L)];
         const int k = j % Ns;
         if (Ns > 1) {
 #pragma unroll
@@ -529,7 +689,7 @@ __device__ __forceinline__ void generic_stage(const cx<R> *src, cx<R> *dst, cons
         Dft<RAD, R>::run(v);
         const int o0 = (j / Ns) * Ns * RAD + k;
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) dst[lds_index<KIND>(l, o0 + q * Ns, n, L)] = v[q];
+        for (int q = 0; q < RAD; ++q) dst[glds<KIND>(l, o0 + q * Ns, n, L)] = v[q];
     }
 }
 
@@ -543,32 +703,39 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
     unsigned *red = reinterpret_cast<unsigned *>(buf1 + (size_t)L * n);
     const cx<R> *tw = reinterpret_cast<const cx<R> *>(a.tw);
     const int tid = threadIdx.x;
-    int l, t;
-    if (KIND == kContiguous) {
-        l = tid / T;
-        t = tid % T;
-    } else {
-        l = tid % L;
-        t = tid / L;
-    }
+    const int l = KIND == kContiguous ? tid / T : tid % L;
+    const int t = KIND == kContiguous ? tid % T : tid / L;
     const bool active = tid < T * L;
     long long q, w;
-    bool valid;
-    line_coords<KIND>(a, l, L, q, w, valid);
-    valid = valid && active;
+    if (KIND == kContiguous) {
+        q = (long long)blockIdx.x * L + l;
+        w = 0;
+    } else {
+        q = ((long long)blockIdx.x % a.ntiles) * L + l;
+        w = (long long)blockIdx.x / a.ntiles;
+    }
+    const bool valid = active && q < (KIND == kContiguous ? a.nlines : a.es);
     const long long es = KIND == kContiguous ? 1 : a.es;
     const long long base = KIND == kContiguous ? q * n : q + w * a.es * n;
+    const bool inv = a.inverse != 0;
     int ebase = 0;
     if constexpr (St::kHalf) {
         const ExpMap &m = a.em;
         ebase = (int)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2);
         if (active && t == 0) red[l] = 0u;
     }
-    // load the line into buf0 (coalesced: consecutive t, consecutive e)
+    // load the line into buf0 (consecutive t read consecutive e)
     if (active) {
-        for (int e = t; e < n; e += T)
-            buf0[lds_index<KIND>(l, e, n, L)] =
-                valid ? load_elem<St>(a, base, es, e, ebase, St::kHalf ? a.em.a3 : 0) : cx<R>{R(0), R(0)};
+        for (int e = t; e < n; e += T) {
+            cx<R> v = {R(0), R(0)};
+            if (valid) {
+                int ex = 0;
+                if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + a.em.a3 * e] : 0;
+                v = St::decode(St::fetch(a.in, base + es * e), ex);
+                if (inv) v = {v.y, v.x};
+            }
+            buf0[glds<KIND>(l, e, n, L)] = v;
+        }
     }
     __syncthreads();
     cx<R> *src = buf0, *dst = buf1;
@@ -596,7 +763,7 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
         float mx = 0.0f;
         if (active)
             for (int e = t; e < n; e += T) {
-                const cx<R> v = src[lds_index<KIND>(l, e, n, L)];
+                const cx<R> v = src[glds<KIND>(l, e, n, L)];
                 mx = fmaxf(mx, fmaxf(fabsf((float)v.x), fabsf((float)v.y)));
             }
         if (active) atomicMax(&red[l], __float_as_uint(mx));
@@ -609,8 +776,8 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
     }
     if (valid) {
         for (int e = t; e < n; e += T) {
-            cx<R> o = src[lds_index<KIND>(l, e, n, L)];
-            if (a.inverse) o.y = -o.y;
+            cx<R> o = src[glds<KIND>(l, e, n, L)];
+            if (inv) o = {o.y, o.x};
             St::store(a.out, base + es * e, o, ex);
         }
     }
@@ -618,21 +785,26 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
 
 // ------------------------------------------------------------ kernel table
 struct Entry {
-    int n, kind, dtype;
-    const void *func;
+    int n, kind, dtype, cand;
+    const void *func[2];  // forward, inverse
     int T, L, block;
     size_t lds;
     RPlan plan;
 };
 
-template <int N, int KIND, class St, int SB, int DT>
-Entry make_entry() {
-    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>)>;
+template <int N, int KIND, class St, int SB, int DT, int EPT = 0, int LREQ = 0, int PAD = 0, int PF = 1>
+Entry make_entry(int cand) {
+    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>), EPT, LREQ, PAD, PF>;
+    static_assert(Cfg::kBlock <= 1024, "block too large");
+    static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    static_assert(Cfg::S >= 1, "length must have a radix plan");
     Entry e;
     e.n = N;
     e.kind = KIND;
     e.dtype = DT;
-    e.func = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND>);
+    e.cand = cand;
+    e.func[0] = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND, false>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND, true>);
     e.T = Cfg::T;
     e.L = Cfg::L;
     e.block = Cfg::kBlock;
@@ -641,25 +813,39 @@ Entry make_entry() {
     return e;
 }
 
-#define CROFT_ENTRIES_FOR(N)                                          \
-    make_entry<N, kContiguous, StC64, 8, kC64>(),                     \
-        make_entry<N, kStrided, StC64, 8, kC64>(),                    \
-        make_entry<N, kContiguous, StC128, 16, kC128>(),              \
-        make_entry<N, kStrided, StC128, 16, kC128>(),                 \
-        make_entry<N, kContiguous, StHalf<false>, 4, kC16F>(),        \
-        make_entry<N, kStrided, StHalf<false>, 4, kC16F>(),           \
-        make_entry<N, kContiguous, StHalf<true>, 4, kC16B>(),         \
-        make_entry<N, kStrided, StHalf<true>, 4, kC16B>()
+// default configuration (candidate 0) of every dtype and pass kind
+#define CROFT_DEFAULTS(N)                                             \
+    make_entry<N, kContiguous, StC64, 8, kC64>(0),                    \
+        make_entry<N, kStrided, StC64, 8, kC64>(0),                   \
+        make_entry<N, kContiguous, StC128, 16, kC128>(0),             \
+        make_entry<N, kStrided, StC128, 16, kC128>(0),                \
+        make_entry<N, kContiguous, StHalf<false>, 4, kC16F>(0),       \
+        make_entry<N, kStrided, StHalf<false>, 4, kC16F>(0),          \
+        make_entry<N, kContiguous, StHalf<true>, 4, kC16B>(0),        \
+        make_entry<N, kStrided, StHalf<true>, 4, kC16B>(0)
+
+// further candidates the autotuner may pick (c64 and half storage):
+// padded LDS lines, no prefetch, 8-line strided tiles, 32-line strided tiles
+// (more elements per thread) without and with prefetch
+#define CROFT_CANDIDATES_ST(N, EW, LW, ST, SB, DT)                        \
+    make_entry<N, kContiguous, ST, SB, DT, 0, 0, 1>(1),                  \
+        make_entry<N, kContiguous, ST, SB, DT, 0, 0, 0, 0>(2),           \
+        make_entry<N, kStrided, ST, SB, DT, 0, 8>(1),                    \
+        make_entry<N, kStrided, ST, SB, DT, 0, 0, 0, 0>(2),              \
+        make_entry<N, kStrided, ST, SB, DT, EW, LW, 0, 0>(3),            \
+        make_entry<N, kStrided, ST, SB, DT, EW, LW, 0, 1>(4)
+#define CROFT_CANDIDATES(N, EW, LW)                                                      \
+    CROFT_CANDIDATES_ST(N, EW, LW, StC64, 8, kC64), CROFT_CANDIDATES_ST(N, EW, LW, StHalf<false>, 4, kC16F), \
+        CROFT_CANDIDATES_ST(N, EW, LW, StHalf<true>, 4, kC16B)
 
 const std::vector<Entry> &table() {
     static const std::vector<Entry> t = {
-        CROFT_ENTRIES_FOR(2),   CROFT_ENTRIES_FOR(4),   CROFT_ENTRIES_FOR(8),
-        CROFT_ENTRIES_FOR(16),  CROFT_ENTRIES_FOR(32),  CROFT_ENTRIES_FOR(64),
-        CROFT_ENTRIES_FOR(128), CROFT_ENTRIES_FOR(256), CROFT_ENTRIES_FOR(512),
-        CROFT_ENTRIES_FOR(1024), CROFT_ENTRIES_FOR(2048), CROFT_ENTRIES_FOR(4096),
-        CROFT_ENTRIES_FOR(48),  CROFT_ENTRIES_FOR(60),  CROFT_ENTRIES_FOR(72),
-        CROFT_ENTRIES_FOR(80),  CROFT_ENTRIES_FOR(96),  CROFT_ENTRIES_FOR(100),
-        CROFT_ENTRIES_FOR(384),
+        CROFT_DEFAULTS(2),   CROFT_DEFAULTS(4),    CROFT_DEFAULTS(8),    CROFT_DEFAULTS(16),
+        CROFT_DEFAULTS(32),  CROFT_DEFAULTS(64),   CROFT_DEFAULTS(128),  CROFT_DEFAULTS(256),
+        CROFT_DEFAULTS(512), CROFT_DEFAULTS(1024), CROFT_DEFAULTS(2048), CROFT_DEFAULTS(4096),
+        CROFT_DEFAULTS(48),  CROFT_DEFAULTS(60),   CROFT_DEFAULTS(72),   CROFT_DEFAULTS(80),
+        CROFT_DEFAULTS(96),  CROFT_DEFAULTS(100),  CROFT_DEFAULTS(384),
+        CROFT_CANDIDATES(256, 16, 32), CROFT_CANDIDATES(512, 16, 32), CROFT_CANDIDATES(1024, 32, 16),
     };
     return t;
 }
@@ -683,21 +869,35 @@ const void *generic_func(int kind, int dtype) {
 
 }  // namespace
 
-bool select_kernel(int n, int kind, int dtype, bool force_generic, KernelConfig *cfg) {
+int kernel_candidates(int n, int kind, int dtype) {
+    int c = 0;
+    for (const Entry &e : table())
+        if (e.n == n && e.kind == kind && e.dtype == dtype) ++c;
+    return c;
+}
+
+bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, KernelConfig *cfg) {
     if (n < 1 || n > kMaxLength) return false;
     if (!force_generic) {
+        const Entry *pick = nullptr;
         for (const Entry &e : table()) {
             if (e.n == n && e.kind == kind && e.dtype == dtype) {
-                cfg->func = e.func;
-                cfg->generic = false;
-                cfg->threads_per_line = e.T;
-                cfg->lines = e.L;
-                cfg->block = e.block;
-                cfg->lds = e.lds;
-                cfg->nstages = e.plan.S;
-                for (int s = 0; s < e.plan.S; ++s) cfg->radix[s] = e.plan.r[s];
-                return true;
+                if (e.cand == 0 && !pick) pick = &e;
+                if (e.cand == cand) pick = &e;
             }
+        }
+        if (pick) {
+            cfg->func = pick->func[0];
+            cfg->func_inv = pick->func[1];
+            cfg->generic = false;
+            cfg->candidate = pick->cand;
+            cfg->threads_per_line = pick->T;
+            cfg->lines = pick->L;
+            cfg->block = pick->block;
+            cfg->lds = pick->lds;
+            cfg->nstages = pick->plan.S;
+            for (int s = 0; s < pick->plan.S; ++s) cfg->radix[s] = pick->plan.r[s];
+            return true;
         }
     }
     const RPlan p = make_rplan(n);
@@ -720,12 +920,12 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, KernelConfig 
     }
     if (L > lds_lines) L = lds_lines;
     if (L < 1) L = 1;
-    // round down to a power of two
-    int p2 = 1;
+    int p2 = 1;  // round down to a power of two
     while (p2 * 2 <= L) p2 *= 2;
     L = p2;
-    cfg->func = generic_func(kind, dtype);
+    cfg->func = cfg->func_inv = generic_func(kind, dtype);
     cfg->generic = true;
+    cfg->candidate = 0;
     cfg->threads_per_line = T;
     cfg->lines = L;
     cfg->block = ((T * L + 63) / 64) * 64;
@@ -735,8 +935,15 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, KernelConfig 
     return true;
 }
 
+long long pass_tiles(const PassLaunch &pl) {
+    const int L = pl.cfg.lines;
+    if (pl.kind == kContiguous) return (pl.nlines + L - 1) / L;
+    return ((pl.es + L - 1) / L) * pl.nw;
+}
+
 hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *out, const int8_t *in_exp,
                        int8_t *out_exp, int inverse, hipStream_t stream) {
+    (void)dtype;
     PassArgs a;
     a.in = in;
     a.out = out;
@@ -752,21 +959,17 @@ hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *ou
     a.L = pl.cfg.lines;
     a.S = pl.cfg.nstages;
     for (int s = 0; s < kMaxStages; ++s) a.radix[s] = pl.cfg.radix[s];
-    long long blocks;
-    if (pl.kind == kContiguous) {
-        a.nlines = pl.nlines;
-        a.ntiles = 1;
-        blocks = (pl.nlines + a.L - 1) / a.L;
-    } else {
-        a.nlines = pl.es;
-        a.ntiles = (pl.es + a.L - 1) / a.L;
-        blocks = a.ntiles * pl.nw;
-    }
-    if (blocks <= 0) return hipSuccess;
+    a.nlines = pl.kind == kContiguous ? pl.nlines : pl.es;
+    a.ntiles = pl.kind == kContiguous ? 1 : (pl.es + a.L - 1) / a.L;
+    a.total = pass_tiles(pl);
+    if (a.total <= 0) return hipSuccess;
+    long long blocks = a.total;
+    if (!pl.cfg.generic && pl.cfg.resident > 0 && pl.cfg.grid_waves > 0)
+        blocks = std::min<long long>(blocks, (long long)pl.cfg.resident * pl.cfg.grid_waves);
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     void *args[] = {&a};
-    return hipLaunchKernel(pl.cfg.func, dim3((unsigned)blocks), dim3(pl.cfg.block), args, pl.cfg.lds,
-                           stream);
+    const void *f = inverse ? pl.cfg.func_inv : pl.cfg.func;
+    return hipLaunchKernel(f, dim3((unsigned)blocks), dim3(pl.cfg.block), args, pl.cfg.lds, stream);
 }
 
 }  // namespace croft

@@ -1,0 +1,62 @@
+// croft_tune.cpp -- wisdom: remembered kernel choices per (length, pass kind,
+// dtype), the FFTW-style cache of the autotuner's results.
+//
+// The choice is a compiled candidate configuration and the persistent grid
+// size (in resident-block waves; 0 = one block per tile).  Choices measured in
+// this process are kept in memory; when the environment variable CROFT_WISDOM
+// names a file, plans also read it and CROFT_MEASURE plans append to it.
+// File format, one choice per line:  n kind dtype candidate waves
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "croft_internal.h"
+
+namespace croft {
+namespace {
+std::mutex g_mu;
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_mem;
+
+bool read_file(const char *path, int n, int kind, int dtype, int *cand, int *waves) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    int a, b, c, d, e;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%d %d %d %d %d", &a, &b, &c, &d, &e) == 5 && a == n && b == kind && c == dtype) {
+            *cand = d;  // the last matching line wins
+            *waves = e;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+}  // namespace
+
+bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const char *path = std::getenv("CROFT_WISDOM");
+    if (path && *path && read_file(path, n, kind, dtype, cand, waves)) return true;
+    auto it = g_mem.find({n, kind, dtype});
+    if (it == g_mem.end()) return false;
+    *cand = it->second.first;
+    *waves = it->second.second;
+    return true;
+}
+
+void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_mem[{n, kind, dtype}] = {cand, waves};
+    const char *path = std::getenv("CROFT_WISDOM");
+    if (!persist || !path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%d %d %d %d %d\n", n, kind, dtype, cand, waves);
+        std::fclose(f);
+    }
+}
+
+}  // namespace croft

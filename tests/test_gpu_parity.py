@@ -209,3 +209,64 @@ def test_execute_argument_errors_on_device():
     with pytest.raises(ValueError, match="out_exp"):
         croft.croft_execute_scaled(hplan, d, None, d, None)
     croft.croft_plan_destroy(hplan)
+
+
+@pytest.mark.parametrize("dtype", [C64, F16], ids=["c64", "f16"])
+@pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20)], ids=str)
+def test_every_compiled_candidate_gives_identical_bits(dtype, shape, tmp_path, monkeypatch):
+    """Every autotuner candidate (and persistent-grid size) runs the same
+    arithmetic in the same order, so the outputs agree bit for bit; the
+    default candidate is checked against the oracle elsewhere."""
+    wisdom = tmp_path / "wisdom.txt"
+    monkeypatch.setenv("CROFT_WISDOM", str(wisdom))
+    nz, ny, nx = shape
+    rng = np.random.Generator(np.random.PCG64(21))
+    if dtype == C64:
+        x = torch.from_numpy((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)).cuda()
+        ein = None
+    else:
+        x = torch.from_numpy(rng.standard_normal(shape + (2,)).astype(np.float16)).cuda()
+        ein = torch.zeros((nz, ny), dtype=torch.int8, device="cuda")
+
+    def run():
+        out = torch.full_like(x, float("nan"))
+        eout = torch.full((ny, nx), 99, dtype=torch.int8, device="cuda")
+        plan = croft.croft_plan_create(nx, ny, nz, dtype, FWD)
+        info = croft.croft_plan_info(plan)
+        if dtype == C64:
+            croft.croft_execute(plan, x, out)
+        else:
+            croft.croft_execute_scaled(plan, x, ein, out, eout)
+        torch.cuda.synchronize()
+        croft.croft_plan_destroy(plan)
+        return out.cpu(), eout.cpu(), info
+
+    wisdom.write_text("")
+    ref, ref_e, info = run()
+    assert not torch.isnan(ref).any()
+    lengths = {(p["n"], p["kind"]) for p in info["passes"]}
+    tried = 0
+    for n, kind in lengths:
+        for cand in range(5):
+            for waves in (0, 1, 3):
+                wisdom.write_text(f"{n} {kind} {dtype} {cand} {waves}\n")
+                got, got_e, ginfo = run()
+                chosen = [p for p in ginfo["passes"] if (p["n"], p["kind"]) == (n, kind)]
+                assert torch.equal(got.view(torch.int32) if dtype == C64 else got.view(torch.int16),
+                                   ref.view(torch.int32) if dtype == C64 else ref.view(torch.int16)), \
+                    (n, kind, cand, waves)
+                assert torch.equal(got_e, ref_e)
+                tried += 1
+    assert tried >= 24
+
+
+def test_measure_flag_autotunes_and_records_wisdom(tmp_path, monkeypatch):
+    wisdom = tmp_path / "w.txt"
+    monkeypatch.setenv("CROFT_WISDOM", str(wisdom))
+    x = synth.normal_c((16, 64, 256), seed=22)
+    seen, ref, _ = run_fft(x, C64)
+    _, y, _ = run_fft(x, C64, flags=croft.CROFT_MEASURE)
+    assert oracle.rel_l2(y, oracle.dft3d(seen)) <= TOL[C64]
+    lines = [l.split() for l in wisdom.read_text().strip().split("\n")]
+    assert {(int(l[0]), int(l[1])) for l in lines} == {(256, 0), (64, 1), (16, 1)}
+    assert np.array_equal(y, ref)
