@@ -337,30 +337,44 @@ int measure_passes(croft_plan *p) {
             const int ncand = kernel_candidates(pl.n, pl.kind, p->dtype);
             float best_ms = 1e30f;
             KernelConfig pick = pl.cfg;
+            // every pass of the plan with this (length, kind): a choice is
+            // timed on all the geometries it will run (e.g. both y and z)
+            std::vector<const PassLaunch *> same;
+            for (auto &ps2 : p->passes)
+                for (const PassLaunch &q : ps2)
+                    if (q.n == pl.n && q.kind == pl.kind) same.push_back(&q);
             for (int c = 0; c < ncand && rc == CROFT_SUCCESS; ++c) {
                 KernelConfig cfg;
                 if (!select_kernel(pl.n, pl.kind, p->dtype, false, c, &cfg) || cfg.candidate != c) continue;
                 if ((rc = prepare_kernel(&cfg)) != CROFT_SUCCESS) break;
-                for (int waves : {1, 2, 0}) {
-                    PassLaunch t = pl;
-                    t.cfg = cfg;
-                    t.cfg.grid_waves = waves;
-                    float ms = 0.f;
-                    for (int rep = 0; rep < 2 && (e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0)) == hipSuccess;
-                         ++rep) {
+                for (int waves : {1, 2, 4, 0}) {
+                    float total = 0.f;
+                    for (const PassLaunch *q : same) {
+                        PassLaunch t = *q;
+                        t.cfg = cfg;
+                        t.cfg.grid_waves = waves;
+                        float best_rep = 1e30f;
+                        e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0);  // warm-up
+                        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                            float ms = 0.f;
+                            e = hipEventRecord(t0, 0);
+                            if (e == hipSuccess) e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0);
+                            if (e == hipSuccess) e = hipEventRecord(t1, 0);
+                            if (e == hipSuccess) e = hipEventSynchronize(t1);
+                            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                            best_rep = std::min(best_rep, ms);
+                        }
+                        if (e != hipSuccess) break;
+                        total += best_rep;
                     }
-                    if (e == hipSuccess) e = hipEventRecord(t0, 0);
-                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0);
-                    if (e == hipSuccess) e = hipEventRecord(t1, 0);
-                    if (e == hipSuccess) e = hipEventSynchronize(t1);
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
                     if (e != hipSuccess) {
                         rc = fail_hip(e, "autotune launch");
                         break;
                     }
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        pick = t.cfg;
+                    if (total < best_ms) {
+                        best_ms = total;
+                        pick = cfg;
+                        pick.grid_waves = waves;
                     }
                 }
             }

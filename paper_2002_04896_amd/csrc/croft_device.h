@@ -1,0 +1,753 @@
+// croft_device.h -- device code of the HIP kernels for gfx950: one axis pass
+// of the 3D FFT (included by the kernel translation units only).
+//
+// A pass runs batched 1D FFTs of length n along one axis of the grid (steps
+// 1, 5 and 9 of the paper's algorithm, Section 4.1).  The paper's pack,
+// all-to-all and unpack steps between them (steps 2-4, 6-8) are the layout
+// change that makes the next axis contiguous; on one GPU no data is moved for
+// it: a strided pass reads a tile of `L` neighbouring lines of the next axis
+// directly (each row of the tile is one contiguous L-element segment), runs
+// the FFT through LDS, and writes the results back in place, so the grid stays
+// in its natural layout and the closing transposes of Section 4.2 are free.
+//
+// Inside a block the 1D FFT is a Stockham autosort FFT (mixed radix 2, 3, 4,
+// 5, 8, 16): stage s with radix R, span Ns (the product of the earlier
+// radices) and k = j mod Ns maps
+//     v[q] = a[j + q N/R] * w_{Ns R}^{q k}       q = 0 .. R-1
+//     V    = DFT_R(v)
+//     b[(j / Ns) Ns R + k + q Ns] = V[q]
+// for every butterfly j < N/R.  The first stage reads global memory and the
+// last writes it (both with consecutive j on consecutive threads); the stages
+// between exchange through LDS.  Twiddles come from a per-length table of
+// w_N^m = exp(-2 pi i m / N) computed on the host in FP64.  The inverse
+// direction swaps real and imaginary parts on load and on store:
+// swap(DFT(swap(x))) is the unnormalised inverse DFT.
+//
+// Half storage: a line is loaded as FP16/BF16 pairs scaled by 2^e of the line
+// that stored each element, computed in FP32, and stored with one new
+// exponent per line chosen from the line's largest |re|, |im|.
+
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "croft_internal.h"
+
+namespace croft {
+namespace dev {
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+struct cx {
+    R x, y;
+};
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+// Floating-point contraction is off for this file (-ffp-contract=off): every
+// fused multiply-add below is written out, so the rounding of each operation
+// is fixed by the source and does not depend on how a configuration is
+// scheduled -- all tile shapes of a length give bit-identical results.
+template <typename R>
+__device__ __forceinline__ R fmaR(R a, R b, R c) {
+    return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {fmaR(a.x, b.x, -(a.y * b.y)), fmaR(a.x, b.y, a.y * b.x)};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.x * s, a.y * s}; }
+// a * (-i)
+template <typename R>
+__device__ __forceinline__ cx<R> mul_mi(cx<R> a) { return {a.y, -a.x}; }
+
+template <typename R>
+struct Kc {
+    static constexpr R rs2 = R(0.70710678118654752440);   // cos(pi/4)
+    static constexpr R c8 = R(0.92387953251128675613);    // cos(pi/8)
+    static constexpr R s8 = R(0.38268343236508977173);    // sin(pi/8)
+    static constexpr R s3 = R(0.86602540378443864676);    // sin(pi/3)
+    static constexpr R c51 = R(0.30901699437494742410);   // cos(2pi/5)
+    static constexpr R c52 = R(-0.80901699437494742410);  // cos(4pi/5)
+    static constexpr R s51 = R(0.95105651629515357212);   // sin(2pi/5)
+    static constexpr R s52 = R(0.58778525229247312917);   // sin(4pi/5)
+};
+
+// ------------------------------------------------- forward DFT codelets
+// In place on v[0..R-1]: V[k] = sum_j v[j] exp(-2 pi i j k / R).
+template <typename R>
+__device__ __forceinline__ void dft4(cx<R> &a0, cx<R> &a1, cx<R> &a2, cx<R> &a3) {
+    const cx<R> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_mi(a1 - a3);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+}
+
+template <int RAD, typename R>
+struct Dft;
+
+template <typename R>
+struct Dft<2, R> {
+    static __device__ __forceinline__ void run(cx<R> *v) {
+        const cx<R> a = v[0];
+        v[0] = a + v[1];
+        v[1] = a - v[1];
+    }
+};
+
+template <typename R>
+struct Dft<3, R> {
+    static __device__ __forceinline__ void run(cx<R> *v) {
+        const cx<R> t = v[1] + v[2], d = v[1] - v[2];
+        const cx<R> m = {fmaR(R(-0.5), t.x, v[0].x), fmaR(R(-0.5), t.y, v[0].y)};
+        const R s = Kc<R>::s3;
+        v[0] = v[0] + t;
+        v[1] = {fmaR(s, d.y, m.x), fmaR(-s, d.x, m.y)};
+        v[2] = {fmaR(-s, d.y, m.x), fmaR(s, d.x, m.y)};
+    }
+};
+
+template <typename R>
+struct Dft<4, R> {
+    static __device__ __forceinline__ void run(cx<R> *v) { dft4(v[0], v[1], v[2], v[3]); }
+};
+
+template <typename R>
+struct Dft<5, R> {
+    static __device__ __forceinline__ void run(cx<R> *v) {
+        using K = Kc<R>;
+        const cx<R> t1 = v[1] + v[4], t2 = v[2] + v[3], d1 = v[1] - v[4], d2 = v[2] - v[3];
+        const cx<R> m1 = {fmaR(K::c52, t2.x, fmaR(K::c51, t1.x, v[0].x)),
+                          fmaR(K::c52, t2.y, fmaR(K::c51, t1.y, v[0].y))};
+        const cx<R> m2 = {fmaR(K::c51, t2.x, fmaR(K::c52, t1.x, v[0].x)),
+                          fmaR(K::c51, t2.y, fmaR(K::c52, t1.y, v[0].y))};
+        const cx<R> n1 = {fmaR(K::s52, d2.x, K::s51 * d1.x), fmaR(K::s52, d2.y, K::s51 * d1.y)};
+        const cx<R> n2 = {fmaR(-K::s51, d2.x, K::s52 * d1.x), fmaR(-K::s51, d2.y, K::s52 * d1.y)};
+        v[0] = v[0] + t1 + t2;
+        v[1] = {m1.x + n1.y, m1.y - n1.x};
+        v[4] = {m1.x - n1.y, m1.y + n1.x};
+        v[2] = {m2.x + n2.y, m2.y - n2.x};
+        v[3] = {m2.x - n2.y, m2.y + n2.x};
+    }
+};
+
+template <typename R>
+struct Dft<8, R> {
+    static __device__ __forceinline__ void run(cx<R> *v) {
+        const R h = Kc<R>::rs2;
+        dft4(v[0], v[2], v[4], v[6]);  // even half -> E0..E3
+        dft4(v[1], v[3], v[5], v[7]);  // odd half  -> O0..O3
+        const cx<R> o1 = {(v[3].x + v[3].y) * h, (v[3].y - v[3].x) * h};   // O1 w8
+        const cx<R> o2 = mul_mi(v[5]);                                      // O2 w8^2
+        const cx<R> o3 = {(v[7].y - v[7].x) * h, -(v[7].x + v[7].y) * h};  // O3 w8^3
+        const cx<R> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+        v[0] = e0 + o0;
+        v[4] = e0 - o0;
+        v[1] = e1 + o1;
+        v[5] = e1 - o1;
+        v[2] = e2 + o2;
+        v[6] = e2 - o2;
+        v[3] = e3 + o3;
+        v[7] = e3 - o3;
+    }
+};
+
+template <typename R>
+struct Dft<16, R> {
+    // 16 = 4 x 4: DFT4 down the columns n2 (inputs 4 n1 + n2), twiddle by
+    // w16^(n2 k1), DFT4 along the rows; output k1 + 4 k2.
+    static __device__ __forceinline__ void run(cx<R> *v) {
+        using K = Kc<R>;
+        for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+        // now v[4 k1 + n2] = A[n2][k1]
+        const cx<R> w1 = {K::c8, -K::s8}, w2 = {K::rs2, -K::rs2}, w3 = {K::s8, -K::c8};
+        const cx<R> w6 = {-K::rs2, -K::rs2}, w9 = {-K::c8, K::s8};
+        v[5] = cmul(v[5], w1);    // (k1 1, n2 1): w^1
+        v[6] = cmul(v[6], w2);    // (1, 2): w^2
+        v[7] = cmul(v[7], w3);    // (1, 3): w^3
+        v[9] = cmul(v[9], w2);    // (2, 1): w^2
+        v[10] = mul_mi(v[10]);    // (2, 2): w^4
+        v[11] = cmul(v[11], w6);  // (2, 3): w^6
+        v[13] = cmul(v[13], w3);  // (3, 1): w^3
+        v[14] = cmul(v[14], w6);  // (3, 2): w^6
+        v[15] = cmul(v[15], w9);  // (3, 3): w^9
+        for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+        // v[4 k1 + k2] = X[k1 + 4 k2]: transpose the 4 x 4 block
+        cx<R> t;
+        t = v[1]; v[1] = v[4]; v[4] = t;
+        t = v[2]; v[2] = v[8]; v[8] = t;
+        t = v[3]; v[3] = v[12]; v[12] = t;
+        t = v[6]; v[6] = v[9]; v[9] = t;
+        t = v[7]; v[7] = v[13]; v[13] = t;
+        t = v[11]; v[11] = v[14]; v[14] = t;
+    }
+};
+
+// ------------------------------------------------------- storage policies
+// fetch() issues the global load and returns the stored bits untouched, so a
+// prefetched tile costs no arithmetic until decode() runs on it.
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+struct StC64 {
+    using R = float;
+    using Raw = vf2;
+    static constexpr bool kHalf = false;
+    static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
+        return reinterpret_cast<const vf2 *>(p)[i];
+    }
+    static __device__ __forceinline__ cx<R> decode(Raw r, int) { return {r.x, r.y}; }
+    static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int) {
+        reinterpret_cast<float2 *>(p)[i] = make_float2(v.x, v.y);
+    }
+    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int) {
+        vf2 w;
+        w.x = v.x;
+        w.y = v.y;
+        *(__attribute__((address_space(1))) vf2 *)p = w;
+    }
+};
+
+struct StC128 {
+    using R = double;
+    using Raw = vd2;
+    static constexpr bool kHalf = false;
+    static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
+        return reinterpret_cast<const vd2 *>(p)[i];
+    }
+    static __device__ __forceinline__ cx<R> decode(Raw r, int) { return {r.x, r.y}; }
+    static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int) {
+        reinterpret_cast<double2 *>(p)[i] = make_double2(v.x, v.y);
+    }
+    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int) {
+        vd2 w;
+        w.x = v.x;
+        w.y = v.y;
+        *(__attribute__((address_space(1))) vd2 *)p = w;
+    }
+};
+
+__device__ __forceinline__ float f16_bits_to_float(unsigned short b) {
+    return __half2float(__ushort_as_half(b));
+}
+__device__ __forceinline__ unsigned short float_to_f16_bits(float f) {
+    return __half_as_ushort(__float2half_rn(f));
+}
+__device__ __forceinline__ float bf16_bits_to_float(unsigned short b) {
+    return __uint_as_float(static_cast<unsigned>(b) << 16);
+}
+// Round to nearest, ties to even, on the upper 16 bits of the binary32 value.
+__device__ __forceinline__ unsigned short float_to_bf16_bits(float f) {
+    const unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);
+    return static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <bool BF>
+struct StHalf {
+    using R = float;
+    using Raw = unsigned;
+    static constexpr bool kHalf = true;
+    static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
+        return reinterpret_cast<const unsigned *>(p)[i];
+    }
+    // value = stored * 2^e
+    static __device__ __forceinline__ cx<R> decode(Raw u, int e) {
+        const unsigned short lo = static_cast<unsigned short>(u & 0xffffu);
+        const unsigned short hi = static_cast<unsigned short>(u >> 16);
+        const float re = BF ? bf16_bits_to_float(lo) : f16_bits_to_float(lo);
+        const float im = BF ? bf16_bits_to_float(hi) : f16_bits_to_float(hi);
+        return {ldexpf(re, e), ldexpf(im, e)};
+    }
+    // stores v * 2^-e, rounded to nearest even
+    static __device__ __forceinline__ unsigned encode(cx<R> v, int e) {
+        const float re = ldexpf(v.x, -e), im = ldexpf(v.y, -e);
+        const unsigned lo = BF ? float_to_bf16_bits(re) : float_to_f16_bits(re);
+        const unsigned hi = BF ? float_to_bf16_bits(im) : float_to_f16_bits(im);
+        return lo | (hi << 16);
+    }
+    static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int e) {
+        reinterpret_cast<unsigned *>(p)[i] = encode(v, e);
+    }
+    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int e) {
+        *(__attribute__((address_space(1))) unsigned *)p = encode(v, e);
+    }
+};
+
+// Exponent for a line whose largest |re|, |im| is mx: the e with
+// mx * 2^-e in [2^14, 2^15); 0 for an all-zero line.
+__device__ __forceinline__ int line_exponent(float mx) {
+    if (!(mx > 0.0f)) return 0;
+    if (!(mx <= 3.402823466e38f)) return 127;
+    int E;
+    frexpf(mx, &E);  // mx = f 2^E, f in [0.5, 1)
+    const int e = E - 15;
+    return e < -128 ? -128 : (e > 127 ? 127 : e);
+}
+
+// The inverse transform is swap(DFT(swap(x))) with swap(a + ib) = b + ia.
+template <bool INV, typename R>
+__device__ __forceinline__ cx<R> maybe_swap(cx<R> v) {
+    if constexpr (INV) return {v.y, v.x};
+    return v;
+}
+
+// --------------------------------------------------------- launch arguments
+struct PassArgs {
+    const void *in;
+    void *out;
+    const void *tw;
+    const int8_t *in_exp;
+    int8_t *out_exp;
+    long long nlines;  // contiguous: lines; strided: p range (== es)
+    long long es;      // element stride
+    long long nw;      // strided: w count
+    long long ntiles;  // strided: tiles of L lines per w
+    long long total;   // tiles in the launch
+    ExpMap em;
+    int inverse;       // runtime-radix kernel only (static kernels take it as a template argument)
+    // runtime-radix kernel only
+    int n, T, L, S;
+    int radix[kMaxStages];
+};
+
+// ------------------------------------------------------ radix plans
+struct RPlan {
+    int n = 1, S = 0, rmax = 1;
+    int r[kMaxStages] = {};
+};
+
+// Factor n into radices: the 5s, then the 3s, then the power of two as
+// radix-8 stages with one radix-4 or radix-16 stage for the remainder
+// (2 and 4 stand alone for n = 2, 4).
+constexpr RPlan make_rplan(int n) {
+    RPlan p;
+    p.n = n;
+    int m = n, c5 = 0, c3 = 0, a2 = 0;
+    while (m % 5 == 0) { m /= 5; ++c5; }
+    while (m % 3 == 0) { m /= 3; ++c3; }
+    while (m % 2 == 0) { m /= 2; ++a2; }
+    if (m != 1) { p.S = -1; return p; }
+    for (int i = 0; i < c5; ++i) p.r[p.S++] = 5;
+    for (int i = 0; i < c3; ++i) p.r[p.S++] = 3;
+    int k = a2 / 3, rem = a2 % 3;
+    if (rem == 1 && k >= 1) {
+        for (int i = 0; i < k - 1; ++i) p.r[p.S++] = 8;
+        p.r[p.S++] = 16;
+    } else {
+        for (int i = 0; i < k; ++i) p.r[p.S++] = 8;
+        if (rem == 1) p.r[p.S++] = 2;
+        if (rem == 2) p.r[p.S++] = 4;
+    }
+    for (int i = 0; i < p.S; ++i) p.rmax = p.r[i] > p.rmax ? p.r[i] : p.rmax;
+    return p;
+}
+
+constexpr int ns_before(const RPlan &p, int s) {
+    int v = 1;
+    for (int i = 0; i < s; ++i) v *= p.r[i];
+    return v;
+}
+// LDS twiddle table: stage s >= 1 holds (r_s - 1) * Ns_s entries,
+// entry (q, k) = w_N^(q k N / (Ns R)) at offset (q - 1) Ns + k.
+constexpr int tw_offset(const RPlan &p, int s) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += (p.r[i] - 1) * ns_before(p, i);
+    return o;
+}
+
+constexpr int floor_pow2(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// LDS budget used to size default tiles: two blocks fit in a CU's 160 KiB.
+constexpr int kLdsLimit = 80 * 1024;
+
+// Compile-time launch shape of a static kernel for length N.
+//   EPT: elements per thread (T = N / EPT threads per line); 0 = the largest
+//        radix, so the largest-radix stages take one butterfly per thread.
+//   LREQ: lines per block; 0 = the default: about 256 threads for contiguous
+//        lines; for strided lines enough neighbouring lines that each row of
+//        the tile is a 128-byte segment, more when T is small, within 1024
+//        threads and the LDS budget.
+//   PAD: contiguous lines only: one padding element per 32 in LDS.
+//   PF: prefetch the next tile's loads while transforming the current one.
+template <int N, int KIND, int STORE_BYTES, int COMPUTE_BYTES, int EPT = 0, int LREQ = 0, int PAD = 0,
+          int PF = 1>
+struct SCfg {
+    static constexpr bool kPrefetch = PF != 0;
+    static constexpr RPlan plan = make_rplan(N);
+    static constexpr int S = plan.S;
+    static constexpr int kEpt = EPT > 0 ? EPT : plan.rmax;
+    static constexpr int T = cmax(1, N / kEpt);
+    static constexpr int kLineStride = (KIND == kContiguous && PAD) ? N + (N + 31) / 32 : N;
+    static constexpr int kTwN = tw_offset(plan, S);
+    static constexpr int kLdsLines = cmax(1, (kLdsLimit - kTwN * COMPUTE_BYTES) / (kLineStride * COMPUTE_BYTES));
+    static constexpr int L = LREQ > 0 ? LREQ
+                             : KIND == kContiguous
+                                 ? floor_pow2(cmax(1, cmin(cmin(256 / T, 256), kLdsLines)))
+                                 : floor_pow2(cmax(1, cmin(cmin(cmax(128 / STORE_BYTES, 256 / T), 1024 / T), kLdsLines)));
+    static constexpr int kBlock = T * L;
+    // lines never straddle a wavefront: stages sync per wave, not per block
+    static constexpr bool kWaveSync = KIND == kContiguous && T <= 64 && (64 % T) == 0;
+    static constexpr size_t kLdsData = (size_t)L * kLineStride * COMPUTE_BYTES;
+    static constexpr size_t kLds = kLdsData + (size_t)kTwN * COMPUTE_BYTES + 4 * (size_t)L;
+};
+
+template <int KIND, int LS, int PAD>
+__device__ __forceinline__ int lds_index(int l, int e, int L) {
+    if constexpr (KIND == kContiguous) return l * LS + e + (PAD ? (e >> 5) : 0);
+    return e * L + l;
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (WAVE) {
+        // all lanes of a line are in this wavefront: order its LDS accesses
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ static kernel
+// A block holds a tile of L lines and loops over tiles with a stride of the
+// grid size; while one tile is transformed the global loads of the next are
+// in flight (they are only decoded when that tile starts).
+template <class Cfg, class St>
+struct Tile {
+    static constexpr int R0 = Cfg::plan.r[0];
+    static constexpr int NB0 = Cfg::plan.n / R0;
+    static constexpr int B0 = (NB0 + Cfg::T - 1) / Cfg::T;
+    // with prefetch: the stored bits (and exponents), decoded when the tile
+    // starts; without: the decoded values
+    static constexpr bool kRaw = Cfg::kPrefetch;
+    using Elem = typename std::conditional<kRaw, typename St::Raw, cx<typename St::R>>::type;
+    Elem e[B0][R0];
+    int ex[(kRaw && St::kHalf) ? B0 : 1][(kRaw && St::kHalf) ? R0 : 1];
+};
+
+struct TileCoord {
+    long long q;      // line coordinate of this thread (contiguous: line; strided: p)
+    long long w;      // strided: line block
+    long long tbase;  // element index of the tile's first element (uniform in the block)
+    bool valid;
+};
+
+// Element index = tbase + lane + (b T + q NB) es: the tile origin and the
+// stage offsets are uniform across the block, the lane part is fixed per
+// thread, so each access costs one address add.
+template <class Cfg, int KIND>
+__device__ __forceinline__ TileCoord tile_coord(const PassArgs &a, long long tx, long long w, int l) {
+    TileCoord c;
+    c.q = tx * Cfg::L + l;
+    c.w = w;
+    c.tbase = KIND == kContiguous ? tx * Cfg::L * Cfg::plan.n : tx * Cfg::L + w * a.es * Cfg::plan.n;
+    c.valid = c.q < (KIND == kContiguous ? a.nlines : a.es);
+    return c;
+}
+
+// Byte offset of the thread's first element from the tile origin; it fits in
+// 32 bits (the planner sends larger strides to the runtime-radix kernel), so
+// an access is a uniform 64-bit base plus this one per-thread register.
+template <class Cfg, class St, int KIND>
+__device__ __forceinline__ unsigned lane_offset(int l, int t, long long es) {
+    const long long e = (KIND == kContiguous ? (long long)l * Cfg::plan.n : (long long)l) + (long long)t * es;
+    return (unsigned)(e * (long long)sizeof(typename St::Raw));
+}
+
+// The tile base is the same in every lane; saying so (readfirstlane) keeps it
+// in scalar registers, so each access is a scalar base plus one 32-bit lane
+// offset register (global address space kept explicit).
+typedef __attribute__((address_space(1))) char gchar;
+
+__device__ __forceinline__ gchar *uniform_gptr(const void *p, long long byte_off) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p) + (unsigned long long)byte_off;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (gchar *)(((unsigned long long)hi << 32) | lo);
+}
+
+template <class St>
+__device__ __forceinline__ typename St::Raw fetch_at(const void *p, long long uniform_elem, unsigned lane_bytes) {
+    using Raw = typename St::Raw;
+    gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(Raw));
+    return *(const __attribute__((address_space(1))) Raw *)(b + lane_bytes);
+}
+
+template <class St>
+__device__ __forceinline__ void store_at(void *p, long long uniform_elem, unsigned lane_bytes,
+                                         cx<typename St::R> v, int ex) {
+    gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(typename St::Raw));
+    St::store_g(b + lane_bytes, v, ex);
+}
+
+template <class Cfg, class St, int KIND, bool INV>
+__device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c, int t, unsigned lane,
+                                           long long es, Tile<Cfg, St> &tl) {
+    using TL = Tile<Cfg, St>;
+    if (!c.valid) return;
+    int ebase = 0;
+    long long ea3 = 0;
+    if constexpr (St::kHalf) {
+        const ExpMap &m = a.em;
+        ebase = (int)((c.q % m.qmod) * m.a0 + (c.q / m.qmod) * m.a1 + c.w * m.a2);
+        ea3 = m.a3;
+    }
+#pragma unroll
+    for (int b = 0; b < TL::B0; ++b) {
+        const int j = t + b * Cfg::T;
+        if ((TL::NB0 % Cfg::T) == 0 || j < TL::NB0) {
+#pragma unroll
+            for (int q = 0; q < TL::R0; ++q) {
+                const long long u = c.tbase + (long long)(b * Cfg::T + q * TL::NB0) * es;
+                const typename St::Raw r = fetch_at<St>(a.in, u, lane);
+                int ex = 0;
+                if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + ea3 * (j + q * TL::NB0)] : 0;
+                if constexpr (TL::kRaw) {
+                    tl.e[b][q] = r;
+                    if constexpr (St::kHalf) tl.ex[b][q] = ex;
+                } else {
+                    tl.e[b][q] = maybe_swap<INV>(St::decode(r, ex));
+                }
+            }
+        }
+    }
+}
+
+template <class Cfg, class St, int KIND, bool INV, int S>
+__device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::R> *lds,
+                                             const cx<typename St::R> *tws, unsigned *red, int t, int l,
+                                             const TileCoord &c, unsigned lane, long long es,
+                                             const Tile<Cfg, St> &tl, int &ex_out) {
+    using R = typename St::R;
+    constexpr int N = Cfg::plan.n;
+    constexpr int T = Cfg::T;
+    constexpr int L = Cfg::L;
+    constexpr int LS = Cfg::kLineStride;
+    constexpr int PAD = LS != N;
+    constexpr int RAD = Cfg::plan.r[S];
+    constexpr int Ns = ns_before(Cfg::plan, S);
+    constexpr int NB = N / RAD;
+    constexpr int B = (NB + T - 1) / T;
+    constexpr bool kGuard = (NB % T) != 0;
+    constexpr bool kLast = (S == Cfg::S - 1);
+    constexpr int kTw = tw_offset(Cfg::plan, S);
+
+    cx<R> v[B][RAD];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + b * T;
+        if (!kGuard || j < NB) {
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) {
+                if constexpr (S == 0) {
+                    if constexpr (Tile<Cfg, St>::kRaw)
+                        v[b][q] = maybe_swap<INV>(St::decode(tl.e[b][q], St::kHalf ? tl.ex[b][q] : 0));
+                    else
+                        v[b][q] = tl.e[b][q];
+                } else {
+                    v[b][q] = lds[lds_index<KIND, LS, PAD>(l, j + q * NB, L)];
+                }
+            }
+            if constexpr (Ns > 1) {
+                const int k = j % Ns;
+#pragma unroll
+                for (int q = 1; q < RAD; ++q) v[b][q] = cmul(v[b][q], tws[kTw + (q - 1) * Ns + k]);
+            }
+            Dft<RAD, R>::run(v[b]);
+        }
+        // keep the scheduler from hoisting the next butterfly's LDS loads
+        // above this one: bounds the registers live in wide tiles
+        if constexpr (B > 1) __builtin_amdgcn_sched_barrier(0);
+    }
+
+    if constexpr (kLast) {
+        // outputs of the last stage: index j + q * NB (Ns * RAD == N)
+        int ex = 0;
+        if constexpr (St::kHalf) {
+            float mx = 0.0f;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int j = t + b * T;
+                if (!kGuard || j < NB) {
+#pragma unroll
+                    for (int q = 0; q < RAD; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[b][q].x), fabsf(v[b][q].y)));
+                }
+            }
+            atomicMax(&red[l], __float_as_uint(mx));
+            stage_sync<Cfg::kWaveSync>();
+            ex = line_exponent(__uint_as_float(red[l]));
+            ex_out = ex;
+        }
+        if (c.valid) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int j = t + b * T;
+                if (!kGuard || j < NB) {
+#pragma unroll
+                    for (int q = 0; q < RAD; ++q) {
+                        const long long u = c.tbase + (long long)(b * T + q * NB) * es;
+                        store_at<St>(a.out, u, lane, maybe_swap<INV>(v[b][q]), ex);
+                    }
+                }
+            }
+        }
+    } else {
+        if constexpr (S > 0) stage_sync<Cfg::kWaveSync>();
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * T;
+            if (!kGuard || j < NB) {
+                const int k = j % Ns;
+                const int o0 = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) lds[lds_index<KIND, LS, PAD>(l, o0 + q * Ns, L)] = v[b][q];
+            }
+        }
+        stage_sync<Cfg::kWaveSync>();
+        static_stage<Cfg, St, KIND, INV, S + 1>(a, lds, tws, red, t, l, c, lane, es, tl, ex_out);
+    }
+}
+
+template <class Cfg>
+__device__ __forceinline__ int tw_source(int i) {
+    // entry i of the LDS twiddle table -> index into the length-N table
+    constexpr RPlan p = Cfg::plan;
+    int src = 0;
+#pragma unroll
+    for (int s = 1; s < kMaxStages; ++s) {
+        if (s < p.S) {
+            const int o = tw_offset(p, s), ns = ns_before(p, s), r = p.r[s];
+            if (i >= o && i < o + (r - 1) * ns) {
+                const int q = (i - o) / ns + 1, k = (i - o) % ns;
+                src = q * k * (p.n / (ns * r));
+            }
+        }
+    }
+    return src;
+}
+
+template <class Cfg, class St, int KIND, bool INV>
+__global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
+    using R = typename St::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int T = Cfg::T;
+    constexpr int L = Cfg::L;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
+    unsigned *red = reinterpret_cast<unsigned *>(smem + Cfg::kLdsData + (size_t)Cfg::kTwN * sizeof(cx<R>));
+    const int tid = threadIdx.x;
+    const int l = KIND == kContiguous ? tid / T : tid % L;
+    const int t = KIND == kContiguous ? tid % T : tid / L;
+
+    if constexpr (Cfg::kTwN > 0) {
+        const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
+        for (int i = tid; i < Cfg::kTwN; i += Cfg::kBlock) tws[i] = W[tw_source<Cfg>(i)];
+        __syncthreads();
+    }
+
+    long long tile = blockIdx.x;
+    if (tile >= a.total) return;
+    const long long G = gridDim.x;
+    const long long es = KIND == kContiguous ? 1 : a.es;
+    // tile -> (tx, w), advanced incrementally by G tiles per iteration
+    long long tx, w, gx = G, gw = 0;
+    if constexpr (KIND == kContiguous) {
+        tx = tile;
+        w = 0;
+    } else {
+        tx = tile % a.ntiles;
+        w = tile / a.ntiles;
+        gx = G % a.ntiles;
+        gw = G / a.ntiles;
+    }
+    Tile<Cfg, St> cur;
+    TileCoord c = tile_coord<Cfg, KIND>(a, tx, w, l);
+    const unsigned lane = lane_offset<Cfg, St, KIND>(l, t, es);
+    if constexpr (Cfg::kPrefetch) fetch_tile<Cfg, St, KIND, INV>(a, c, t, lane, es, cur);
+    for (;;) {
+        const long long nt = tile + G;
+        const bool more = nt < a.total;
+        long long ntx = tx + gx, nw = w + gw;
+        if (KIND != kContiguous && ntx >= a.ntiles) {
+            ntx -= a.ntiles;
+            nw += 1;
+        }
+        const TileCoord nc = tile_coord<Cfg, KIND>(a, ntx, nw, l);
+        Tile<Cfg, St> nxt;
+        if constexpr (Cfg::kPrefetch) {
+            if (more) fetch_tile<Cfg, St, KIND, INV>(a, nc, t, lane, es, nxt);
+        } else {
+            fetch_tile<Cfg, St, KIND, INV>(a, c, t, lane, es, cur);
+        }
+
+        int ex = 0;
+        if constexpr (St::kHalf) {
+            if (t == 0) red[l] = 0u;
+            stage_sync<Cfg::kWaveSync>();
+        }
+        static_stage<Cfg, St, KIND, INV, 0>(a, lds, tws, red, t, l, c, lane, es, cur, ex);
+        if constexpr (St::kHalf) {
+            if (c.valid && t == 0 && a.out_exp) {
+                const ExpMap &m = a.em;
+                a.out_exp[(c.q % m.qmod) * m.b0 + (c.q / m.qmod) * m.b1 + c.w * m.b2] = (int8_t)ex;
+            }
+        }
+        if (!more) break;
+        // the next tile overwrites LDS that this one read last
+        stage_sync<Cfg::kWaveSync>();
+        if constexpr (Cfg::kPrefetch) cur = nxt;
+        c = nc;
+        tile = nt;
+        tx = ntx;
+        w = nw;
+    }
+}
+
+// ------------------------------------------------------------ kernel table
+struct Entry {
+    int n, kind, dtype, cand;
+    const void *func[2];  // forward, inverse
+    int T, L, block;
+    size_t lds;
+    RPlan plan;
+};
+
+template <int N, int KIND, class St, int SB, int DT, int EPT = 0, int LREQ = 0, int PAD = 0, int PF = 1>
+Entry make_entry(int cand) {
+    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>), EPT, LREQ, PAD, PF>;
+    static_assert(Cfg::kBlock <= 1024, "block too large");
+    static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    static_assert(Cfg::S >= 1, "length must have a radix plan");
+    Entry e;
+    e.n = N;
+    e.kind = KIND;
+    e.dtype = DT;
+    e.cand = cand;
+    e.func[0] = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND, false>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND, true>);
+    e.T = Cfg::T;
+    e.L = Cfg::L;
+    e.block = Cfg::kBlock;
+    e.lds = Cfg::kLds;
+    e.plan = Cfg::plan;
+    return e;
+}
+
+}  // namespace dev
+}  // namespace croft

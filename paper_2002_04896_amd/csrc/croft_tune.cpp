@@ -6,6 +6,9 @@
 // this process are kept in memory; when the environment variable CROFT_WISDOM
 // names a file, plans also read it and CROFT_MEASURE plans append to it.
 // File format, one choice per line:  n kind dtype candidate waves
+// Lookup order: the CROFT_WISDOM file, choices measured in this process, the
+// built-in table below (measured on an MI355X with CROFT_MEASURE on cubic
+// grids), then candidate 0 with one resident wave.
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -16,6 +19,19 @@
 
 namespace croft {
 namespace {
+struct Builtin {
+    int n, kind, dtype, cand, waves;
+};
+// n kind dtype candidate waves
+const Builtin kBuiltin[] = {
+    // complex64
+    {512, 0, 0, 1, 0}, {512, 1, 0, 2, 4}, {256, 0, 0, 1, 0}, {256, 1, 0, 1, 0}, {128, 0, 0, 1, 0},
+    // complex128
+    {512, 0, 1, 1, 0}, {512, 1, 1, 2, 2}, {256, 1, 1, 2, 0},
+    // FP16 / BF16 storage
+    {512, 0, 2, 2, 4}, {512, 1, 2, 1, 2}, {512, 0, 3, 2, 4}, {512, 1, 3, 1, 2},
+};
+
 std::mutex g_mu;
 std::map<std::tuple<int, int, int>, std::pair<int, int>> g_mem;
 
@@ -42,10 +58,19 @@ bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves) {
     const char *path = std::getenv("CROFT_WISDOM");
     if (path && *path && read_file(path, n, kind, dtype, cand, waves)) return true;
     auto it = g_mem.find({n, kind, dtype});
-    if (it == g_mem.end()) return false;
-    *cand = it->second.first;
-    *waves = it->second.second;
-    return true;
+    if (it != g_mem.end()) {
+        *cand = it->second.first;
+        *waves = it->second.second;
+        return true;
+    }
+    for (const Builtin &b : kBuiltin) {
+        if (b.n == n && b.kind == kind && b.dtype == dtype) {
+            *cand = b.cand;
+            *waves = b.waves;
+            return true;
+        }
+    }
+    return false;
 }
 
 void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist) {
