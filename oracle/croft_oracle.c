@@ -181,31 +181,43 @@ int oracle_dft3d_lines(int nx, int ny, int nz, const double *in, int sign,
     make_table(nx, tx, tx + nx);
     make_table(ny, ty, ty + ny);
     make_table(nz, tz, tz + nz);
-    /* red[i][x] = sum_z e_z(kz z) sum_y e_y(ky y) X(x,y,z), parallel over (i, x). */
-#pragma omp parallel for collapse(2) schedule(static)
+    /* red[i][x] = sum_z e_z(kz z) sum_y e_y(ky y) X(x,y,z), parallel over
+     * (i, block of XB consecutive x); the x loop is innermost so rows are read
+     * contiguously.  For each x the sums run in the order written above. */
+    enum { XB = 64 };
+    const int nxb = (nx + XB - 1) / XB;
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
     for (int i = 0; i < nsamp; ++i) {
-        for (int x = 0; x < nx; ++x) {
-            double sr = 0.0, si = 0.0;
+        for (int xb = 0; xb < nxb; ++xb) {
+            const int x0 = xb * XB, x1 = (x0 + XB < nx) ? x0 + XB : nx;
+            double sr[XB], si[XB], pr[XB], pi[XB];
+            for (int x = x0; x < x1; ++x) sr[x - x0] = si[x - x0] = 0.0;
             int mz = 0;
             for (int z = 0; z < nz; ++z) {
-                double pr = 0.0, pi = 0.0;
+                for (int x = x0; x < x1; ++x) pr[x - x0] = pi[x - x0] = 0.0;
                 int my = 0;
                 for (int y = 0; y < ny; ++y) {
-                    const double *v = in + 2 * (x + (long)nx * (y + (long)ny * z));
                     const double wr = ty[my], wi = sign * ty[ny + my];
-                    pr += v[0] * wr - v[1] * wi;
-                    pi += v[0] * wi + v[1] * wr;
+                    const double *v = in + 2 * ((long)nx * (y + (long)ny * z));
+                    for (int x = x0; x < x1; ++x) {
+                        pr[x - x0] += v[2 * x] * wr - v[2 * x + 1] * wi;
+                        pi[x - x0] += v[2 * x] * wi + v[2 * x + 1] * wr;
+                    }
                     my += ky[i];
                     if (my >= ny) my -= ny;
                 }
                 const double wr = tz[mz], wi = sign * tz[nz + mz];
-                sr += pr * wr - pi * wi;
-                si += pr * wi + pi * wr;
+                for (int x = x0; x < x1; ++x) {
+                    sr[x - x0] += pr[x - x0] * wr - pi[x - x0] * wi;
+                    si[x - x0] += pr[x - x0] * wi + pi[x - x0] * wr;
+                }
                 mz += kz[i];
                 if (mz >= nz) mz -= nz;
             }
-            red[2 * ((long)i * nx + x)] = sr;
-            red[2 * ((long)i * nx + x) + 1] = si;
+            for (int x = x0; x < x1; ++x) {
+                red[2 * ((long)i * nx + x)] = sr[x - x0];
+                red[2 * ((long)i * nx + x) + 1] = si[x - x0];
+            }
         }
     }
     for (int i = 0; i < nsamp; ++i) {
