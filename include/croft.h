@@ -83,7 +83,12 @@ enum croft_flags {
     CROFT_ESTIMATE = 0,       /* default heuristics, no device timing at create */
     CROFT_MEASURE = 1,        /* time candidate configurations at create (autotune) */
     CROFT_FORCE_GENERIC = 2,  /* use the runtime-radix kernels for every pass */
-    CROFT_NO_WISDOM = 4       /* MEASURE: neither read nor write the wisdom file */
+    CROFT_NO_WISDOM = 4,      /* MEASURE: neither read nor write the wisdom file */
+    CROFT_PERSISTENT = 8      /* batched plans: one persistent launch for every pass of every
+                                 grid (work handed out by an atomic ticket in pass order, a grid's
+                                 pass waiting for its previous pass), instead of one launch per pass.
+                                 Currently disabled: plan creation with this flag fails with
+                                 CROFT_ERR_UNSUPPORTED_DTYPE. */
 };
 
 /* Create a plan for one nx x ny x nz transform (the paper's problem statement,
@@ -138,9 +143,19 @@ croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, in
 int croft_plan_batched_offsets(croft_plan_t plan, size_t *elem_offsets);
 
 /* Run every transform of a batched plan: one launch per axis pass covering
- * all grids, replayed from a HIP graph captured on first use for the given
- * (in, out, stream).  Same in/out rules as croft_execute. */
+ * all grids (or one persistent launch with CROFT_PERSISTENT), replayed from a
+ * HIP graph captured on first use for the given (in, out, stream).  Grids
+ * whose lengths the batched kernels do not compile (any outside 48, 60, 64,
+ * 72, 80, 96, 100, 128) run with launches of their own inside the same graph.
+ * Same in/out rules as croft_execute. */
 int croft_execute_batched(croft_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/* Waits for the device and reports whether a persistent batched launch of
+ * this plan ever had to give up waiting for a previous pass (device_status
+ * 1; the results of that execute are then invalid) -- 0 otherwise and for
+ * plans without such a launch.  Synchronising; a diagnostic, not for hot
+ * paths. */
+int croft_plan_status(croft_plan_t plan, int *device_status);
 
 /* Description of a plan, filled by croft_plan_info. */
 #define CROFT_MAX_PASSES 8

@@ -28,7 +28,7 @@ CROFT_ERR_UNSUPPORTED_DTYPE = 3
 CROFT_ERR_OUT_OF_MEMORY = 4
 CROFT_ERR_HIP = 5
 CROFT_ERR_INTERNAL = 6
-CROFT_ESTIMATE, CROFT_MEASURE, CROFT_FORCE_GENERIC, CROFT_NO_WISDOM = 0, 1, 2, 4
+CROFT_ESTIMATE, CROFT_MEASURE, CROFT_FORCE_GENERIC, CROFT_NO_WISDOM, CROFT_PERSISTENT = 0, 1, 2, 4, 8
 CROFT_MAX_PASSES = 8
 CROFT_MAX_STAGES = 12
 
@@ -37,7 +37,7 @@ EXPORTED = (
     "croft_plan_create", "croft_plan_create_ex", "croft_execute", "croft_execute_scaled",
     "croft_plan_destroy", "croft_last_error", "croft_plan_create_batched",
     "croft_plan_batched_offsets", "croft_execute_batched", "croft_plan_info",
-    "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read",
+    "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read", "croft_plan_status",
 )
 
 
@@ -109,6 +109,8 @@ def load():
     lib.croft_plan_info.restype = i
     lib.croft_plan_describe.argtypes = [i, i, i, i, i, ctypes.c_char_p, ctypes.c_size_t]
     lib.croft_plan_describe.restype = i
+    lib.croft_plan_status.argtypes = [p, ctypes.POINTER(ctypes.c_int)]
+    lib.croft_plan_status.restype = i
     lib.croft_plan_profile.argtypes = [p, i]
     lib.croft_plan_profile.restype = i
     lib.croft_plan_profile_read.argtypes = [p, ctypes.POINTER(ctypes.c_double), i,
@@ -204,6 +206,13 @@ def croft_plan_describe(nx, ny, nz, dtype=CROFT_C64, dir=CROFT_FORWARD) -> str:
     buf = ctypes.create_string_buffer(8192)
     _check(load().croft_plan_describe(nx, ny, nz, dtype, dir, buf, len(buf)))
     return buf.value.decode()
+
+
+def croft_plan_status(plan) -> int:
+    """Device status word of the plan's persistent batched launch (0 = fine)."""
+    v = ctypes.c_int(0)
+    _check(load().croft_plan_status(plan, ctypes.byref(v)))
+    return v.value
 
 
 def croft_plan_profile(plan, enable: bool) -> None:

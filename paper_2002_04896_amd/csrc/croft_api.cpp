@@ -53,6 +53,17 @@ struct croft_plan {
     // slab schedule
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    // batched form: one launch per pass over the grids the batched kernel
+    // compiles (device segment tables), the others grid by grid
+    bool batched = false;
+    void *bitems = nullptr;            // all segments, pass by pass (device)
+    int bbegin[4] = {0, 0, 0, 0};      // segments of pass p: [bbegin[p], bbegin[p + 1])
+    long long btiles[3] = {0, 0, 0};   // tiles of pass p
+    size_t blds[3] = {0, 0, 0};
+    unsigned *bcounters = nullptr;     // persistent launch: ticket + per-segment done counts
+    unsigned *bstatus = nullptr;       // persistent launch: set if a wait gave up
+    int bresident = 0;                 // persistent launch: blocks held at once
+    std::vector<size_t> loose;  // grids run with their own launches
     // batched form: graph cache
     hipGraphExec_t graph = nullptr;
     const void *graph_in = nullptr;
@@ -201,6 +212,8 @@ void destroy_plan(croft_plan *p) {
     }
     if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    if (p->bitems) (void)hipFree(p->bitems);
+    if (p->bcounters) (void)hipFree(p->bcounters);
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     for (auto &v : p->prof)
         for (auto &pr : v) {
@@ -393,6 +406,80 @@ int measure_passes(croft_plan *p) {
     return CROFT_SUCCESS;
 }
 
+// Batched plans: the segment table of the batched kernels (one segment per
+// grid and pass, pass by pass), and the persistent launch's counters.
+int build_batch_tables(croft_plan *p) {
+    const bool usable = (p->dtype == CROFT_C64 || p->dtype == CROFT_C128) && !(p->flags & CROFT_FORCE_GENERIC);
+    const size_t ib = batch_item_bytes();
+    std::vector<size_t> grids;  // grids in the table
+    for (size_t g = 0; g < p->grids.size(); ++g) {
+        const std::vector<PassLaunch> &ps = p->passes[g];
+        bool ok = usable && ps.size() <= 3;
+        for (const PassLaunch &pl : ps) ok = ok && batch_code(pl.n, pl.kind) >= 0;
+        (ok ? grids : p->loose).push_back(g);
+    }
+    std::vector<char> host;
+    std::vector<int> seg_of(p->grids.size() * 3, -1);  // (grid, pass) -> segment index
+    std::vector<long long> seg_total;
+    int nseg = 0;
+    for (int i = 0; i < 3; ++i) {
+        p->bbegin[i] = nseg;
+        for (size_t g : grids) {
+            const std::vector<PassLaunch> &ps = p->passes[g];
+            if ((size_t)i >= ps.size()) continue;
+            const PassLaunch &pl = ps[i];
+            BatchConfig bc;
+            const int code = batch_code(pl.n, pl.kind);
+            if (!batch_config(code, p->dtype, &bc)) return fail(CROFT_ERR_INTERNAL, "batch configuration %d", code);
+            long long ntiles, total;
+            if (pl.kind == kContiguous) {
+                ntiles = 1;
+                total = (pl.nlines + bc.lines - 1) / bc.lines;
+            } else {
+                ntiles = (pl.es + bc.lines - 1) / bc.lines;
+                total = ntiles * pl.nw;
+            }
+            const int dep = i > 0 ? seg_of[g * 3 + i - 1] : -1;
+            host.resize(host.size() + ib);
+            batch_item_fill(host.data() + host.size() - ib, (long long)p->offsets[g], p->btiles[i], pl.es,
+                            pl.kind == kContiguous ? pl.nlines : pl.es, pl.nw, ntiles, total, pl.tw, code, i == 0,
+                            dep, dep >= 0 ? seg_total[dep] : 0);
+            seg_of[g * 3 + i] = nseg++;
+            seg_total.push_back(total);
+            p->btiles[i] += total;
+            p->blds[i] = std::max(p->blds[i], bc.lds);
+        }
+    }
+    p->bbegin[3] = nseg;
+    if (!nseg) return CROFT_SUCCESS;
+    hipError_t e = hipMalloc(&p->bitems, host.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&p->bcounters, sizeof(unsigned) * (size_t)(nseg + 2));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CROFT_ERR_OUT_OF_MEMORY, "batch tables: %s", hipGetErrorString(e));
+    }
+    p->bstatus = p->bcounters + nseg + 1;
+    p->work_bytes += host.size() + sizeof(unsigned) * (size_t)(nseg + 2);
+    if ((e = hipMemcpy(p->bitems, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail_hip(e, "batch table upload");
+    if ((e = hipMemset(p->bcounters, 0, sizeof(unsigned) * (size_t)(nseg + 2))) != hipSuccess)
+        return fail_hip(e, "batch counters");
+    const size_t lds = std::max({p->blds[0], p->blds[1], p->blds[2]});
+    for (int inv = 0; inv < 2; ++inv) {
+        const void *fs[2] = {batch_kernel(p->dtype, inv), batch_persistent_kernel(p->dtype, inv)};
+        for (const void *f : fs) {
+            if (lds > 65536 &&
+                (e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+                return fail_hip(e, "LDS attribute");
+        }
+    }
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_persistent_kernel(p->dtype, 0), 256, lds);
+    if (e != hipSuccess) return fail_hip(e, "occupancy query");
+    p->bresident = std::max(1, nb) * std::max(1, device_cus());
+    return CROFT_SUCCESS;
+}
+
 croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int flags, int slabs) {
     croft_plan *p = new (std::nothrow) croft_plan;
     if (!p) {
@@ -423,7 +510,9 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
         delete p;
         return nullptr;
     }
-    if (attach_resources(p) != CROFT_SUCCESS || ((flags & CROFT_MEASURE) && measure_passes(p) != CROFT_SUCCESS)) {
+    p->batched = grids.size() > 1;
+    if (attach_resources(p) != CROFT_SUCCESS || ((flags & CROFT_MEASURE) && measure_passes(p) != CROFT_SUCCESS) ||
+        (p->batched && build_batch_tables(p) != CROFT_SUCCESS)) {
         std::string msg = g_last_error;
         destroy_plan(p);
         g_last_error = msg;
@@ -540,6 +629,50 @@ int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, in
     return CROFT_SUCCESS;
 }
 
+// All transforms of a batched plan: one launch per pass for the grids the
+// batched kernel compiles, then the remaining grids with their own launches.
+int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    const size_t eb = element_bytes(p->dtype);
+    const int inv = p->dir == CROFT_BACKWARD;
+    const size_t ib = batch_item_bytes();
+    const long long tb[4] = {0, p->btiles[0], p->btiles[0] + p->btiles[1], p->btiles[0] + p->btiles[1] + p->btiles[2]};
+    const int nlaunch = (p->flags & CROFT_PERSISTENT) ? (p->bbegin[3] > 0 ? 1 : 0) : 3;
+    for (int i = 0; i < nlaunch; ++i) {
+        const int n = p->bbegin[i + 1] - p->bbegin[i];
+        if (!(p->flags & CROFT_PERSISTENT) && n == 0) continue;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (prof) {
+            a = pool_event(p);
+            b = pool_event(p);
+            if (!a || !b) return fail(CROFT_ERR_HIP, "profiling event creation failed");
+            (void)hipEventRecord(a, s);
+        }
+        hipError_t e;
+        if (p->flags & CROFT_PERSISTENT) {
+            const size_t lds = std::max({p->blds[0], p->blds[1], p->blds[2]});
+            const int blocks = (int)std::min<long long>(p->bresident, tb[3]);
+            e = launch_batch_persistent(p->bitems, p->bbegin, tb, p->bcounters, (unsigned)(p->bbegin[3] + 1),
+                                        p->bstatus, blocks, lds, p->dtype, inv, in, out, s);
+        } else {
+            e = launch_batch((const char *)p->bitems + (size_t)p->bbegin[i] * ib, n, p->btiles[i], p->blds[i],
+                             p->dtype, inv, in, out, s);
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e, "batched kernel launch");
+        if (prof) {
+            (void)hipEventRecord(b, s);
+            prof->push_back({a, b});
+        }
+    }
+    for (size_t g : p->loose) {
+        const int rc = run_grid(p, g, (const char *)in + p->offsets[g] * eb, (char *)out + p->offsets[g] * eb,
+                                nullptr, nullptr, s, prof);
+        if (rc != CROFT_SUCCESS) return rc;
+    }
+    return CROFT_SUCCESS;
+}
+
 int check_buffers(croft_plan *p, const void *in, const void *out) {
     if (!in || !out) return fail(CROFT_ERR_INVALID_VALUE, "NULL data pointer");
     const size_t bytes = p->offsets.back() * element_bytes(p->dtype);
@@ -631,8 +764,15 @@ croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, in
         fail(CROFT_ERR_UNSUPPORTED_DTYPE, "batched plans take CROFT_C64 or CROFT_C128");
         return nullptr;
     }
-    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
+    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM | CROFT_PERSISTENT)) {
         fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
+        return nullptr;
+    }
+    if (flags & CROFT_PERSISTENT) {
+        // The single persistent launch (blocks waiting on other blocks' done
+        // counts) stalled in its first device test and is switched off until
+        // the cause is established; batched plans use one launch per pass.
+        fail(CROFT_ERR_UNSUPPORTED_DTYPE, "CROFT_PERSISTENT is disabled in this version");
         return nullptr;
     }
     std::vector<Geometry> grids;
@@ -662,12 +802,9 @@ int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t
     if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
     int rc = check_buffers(p, in, out);
     if (rc != CROFT_SUCCESS) return rc;
-    const size_t eb = element_bytes(p->dtype);
     if (p->profiling) {
         std::vector<std::pair<hipEvent_t, hipEvent_t>> rec;
-        for (size_t g = 0; g < p->grids.size() && rc == CROFT_SUCCESS; ++g)
-            rc = run_grid(p, g, (const char *)in + p->offsets[g] * eb, (char *)out + p->offsets[g] * eb, nullptr,
-                          nullptr, stream, &rec);
+        rc = run_batch(p, in, out, stream, &rec);
         p->prof.push_back(std::move(rec));
         return rc;
     }
@@ -684,9 +821,7 @@ int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t
             (void)hipStreamDestroy(cap);
             return fail_hip(e, "begin capture");
         }
-        for (size_t g = 0; g < p->grids.size() && rc == CROFT_SUCCESS; ++g)
-            rc = run_grid(p, g, (const char *)in + p->offsets[g] * eb, (char *)out + p->offsets[g] * eb, nullptr,
-                          nullptr, cap, nullptr);
+        rc = run_batch(p, in, out, cap, nullptr);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cap, &graph);
         (void)hipStreamDestroy(cap);
@@ -793,6 +928,17 @@ int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, s
         std::memcpy(buf, s.data(), n);
         buf[n] = '\0';
     }
+    return CROFT_SUCCESS;
+}
+
+int croft_plan_status(croft_plan_t p, int *device_status) {
+    if (!p || !device_status) return fail(CROFT_ERR_INVALID_VALUE, "NULL argument");
+    *device_status = 0;
+    if (!p->bstatus) return CROFT_SUCCESS;
+    unsigned v = 0;
+    const hipError_t e = hipMemcpy(&v, p->bstatus, sizeof v, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail_hip(e, "status read");
+    *device_status = (int)v;
     return CROFT_SUCCESS;
 }
 

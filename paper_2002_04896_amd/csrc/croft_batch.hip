@@ -1,0 +1,138 @@
+// croft_batch.hip -- the batched form: one launch per axis pass covering the
+// tiles of every grid in a batch (compiled lengths 48, 60, 64, 72, 80, 96,
+// 100, 128; complex64 and complex128).
+#include <hip/hip_runtime.h>
+
+#include "croft_device.h"
+#include "croft_internal.h"
+
+namespace croft {
+using namespace dev;
+
+namespace {
+// Zeroes the ticket and done counters before a persistent launch (a kernel,
+// not a memset, so that the launch can be captured in a graph).
+__global__ void __launch_bounds__(256) batch_reset(unsigned *counters, unsigned n, unsigned *status) {
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0u;
+}
+}  // namespace
+
+int batch_code(int n, int kind) {
+    for (int i = 0; i < 8; ++i)
+        if (kBatchLengths[i] == n) return 2 * i + (kind == kStrided ? 1 : 0);
+    return -1;
+}
+
+namespace {
+template <class St>
+void config_of(int code, BatchConfig *c) {
+    const int i = code / 2;
+    const int kind = code % 2;
+    c->n = kBatchLengths[i];
+    c->kind = kind;
+    c->threads_per_line = batch_threads(c->n);
+    c->lines = 256 / c->threads_per_line;
+    // same formula as SCfg::kLds for these configurations
+    size_t lds = 0;
+    switch (code) {
+#define CROFT_LDS(I)                                                   \
+    case 2 * I: lds = BCfg<kBatchLengths[I], kContiguous, St>::kLds; break; \
+    case 2 * I + 1: lds = BCfg<kBatchLengths[I], kStrided, St>::kLds; break;
+        CROFT_LDS(0) CROFT_LDS(1) CROFT_LDS(2) CROFT_LDS(3) CROFT_LDS(4) CROFT_LDS(5) CROFT_LDS(6) CROFT_LDS(7)
+#undef CROFT_LDS
+        default: break;
+    }
+    c->lds = lds;
+}
+}  // namespace
+
+bool batch_config(int code, int dtype, BatchConfig *c) {
+    if (code < 0 || code >= 16) return false;
+    if (dtype == kC64) config_of<StC64>(code, c);
+    else if (dtype == kC128) config_of<StC128>(code, c);
+    else return false;
+    return true;
+}
+
+const void *batch_kernel(int dtype, int inverse) {
+    if (dtype == kC64)
+        return inverse ? reinterpret_cast<const void *>(&fft_batch<StC64, true>)
+                       : reinterpret_cast<const void *>(&fft_batch<StC64, false>);
+    if (dtype == kC128)
+        return inverse ? reinterpret_cast<const void *>(&fft_batch<StC128, true>)
+                       : reinterpret_cast<const void *>(&fft_batch<StC128, false>);
+    return nullptr;
+}
+
+hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t lds, int dtype, int inverse,
+                        const void *in, void *out, hipStream_t stream) {
+    if (tiles <= 0 || nitems <= 0) return hipSuccess;
+    if (tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    BatchArgs b;
+    b.items = reinterpret_cast<const BatchItem *>(items);
+    b.nitems = nitems;
+    b.in = in;
+    b.out = out;
+    void *args[] = {&b};
+    return hipLaunchKernel(batch_kernel(dtype, inverse), dim3((unsigned)tiles), dim3(256), args, lds, stream);
+}
+
+size_t batch_item_bytes() { return sizeof(BatchItem); }
+
+const void *batch_persistent_kernel(int dtype, int inverse) {
+    if (dtype == kC64)
+        return inverse ? reinterpret_cast<const void *>(&fft_batch_persistent<StC64, true>)
+                       : reinterpret_cast<const void *>(&fft_batch_persistent<StC64, false>);
+    if (dtype == kC128)
+        return inverse ? reinterpret_cast<const void *>(&fft_batch_persistent<StC128, true>)
+                       : reinterpret_cast<const void *>(&fft_batch_persistent<StC128, false>);
+    return nullptr;
+}
+
+hipError_t launch_batch_persistent(const void *items, const int item_begin[4], const long long tile_begin[4],
+                                   unsigned *counters, unsigned ncounters, unsigned *status, int blocks,
+                                   size_t lds, int dtype, int inverse, const void *in, void *out,
+                                   hipStream_t stream) {
+    if (tile_begin[3] <= 0) return hipSuccess;
+    if (tile_begin[3] > 0xffffffffLL) return hipErrorInvalidConfiguration;
+    void *rargs[] = {&counters, &ncounters, &status};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset), dim3(1), dim3(256), rargs, 0,
+                                   stream);
+    if (e != hipSuccess) return e;
+    BatchPersistentArgs b;
+    b.items = reinterpret_cast<const BatchItem *>(items);
+    for (int i = 0; i < 4; ++i) {
+        b.item_begin[i] = item_begin[i];
+        b.tile_begin[i] = tile_begin[i];
+    }
+    b.counters = counters;
+    b.status = status;
+    b.in = in;
+    b.out = out;
+    b.spin_limit = 1u << 24;
+    void *args[] = {&b};
+    return hipLaunchKernel(batch_persistent_kernel(dtype, inverse), dim3((unsigned)blocks), dim3(256), args, lds,
+                           stream);
+}
+
+void batch_item_fill(void *dst, long long offset, long long tile_begin, long long es, long long nlines,
+                     long long nw, long long ntiles, long long total, const void *tw, int code, int from_in,
+                     int dep, long long dep_total) {
+    BatchItem it;
+    it.offset = offset;
+    it.tile_begin = tile_begin;
+    it.es = es;
+    it.nlines = nlines;
+    it.nw = nw;
+    it.ntiles = ntiles;
+    it.total = total;
+    it.tw = tw;
+    it.code = code;
+    it.from_in = from_in;
+    it.dep = dep;
+    it.dep_total = dep_total;
+    *reinterpret_cast<BatchItem *>(dst) = it;
+}
+
+}  // namespace croft

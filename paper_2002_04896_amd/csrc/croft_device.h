@@ -719,6 +719,170 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
     }
 }
 
+// ------------------------------------------------------------ batched form
+// One launch runs one pass of many grids of uneven sizes: a block takes one
+// tile of one (grid, pass) segment, found by binary search over the segments'
+// first tiles.  Every length uses 256 threads per block (T = 4 or 8 threads
+// per line, 256 / T lines per tile), so one kernel serves all of them; the
+// arithmetic per butterfly is the same as in the single-grid kernels.
+struct BatchItem {
+    long long offset;      // element offset of the grid in the packed buffers
+    long long tile_begin;  // first tile of this segment within the launch
+    long long es, nlines, nw, ntiles, total;
+    const void *tw;        // twiddle table of the segment's length
+    int code;              // compiled (length, kind), see batch_code
+    int from_in;           // 1: the segment reads the `in` buffer (the grid's first pass)
+    int dep;               // persistent launch: index of the grid's previous-pass segment, -1 if none
+    long long dep_total;   // tiles of that segment
+};
+
+struct BatchArgs {
+    const BatchItem *items;
+    int nitems;
+    const void *in;
+    void *out;
+};
+
+// Persistent launch over all passes of all grids: work is handed out by an
+// atomic ticket in (pass, grid, tile) order; a segment waits until its grid's
+// previous pass has counted all its tiles done.  A block only ever waits on
+// lower tickets, which blocks that are already running hold, so the launch
+// cannot deadlock whatever the number of resident blocks.
+struct BatchPersistentArgs {
+    const BatchItem *items;     // all segments, pass by pass
+    int item_begin[4];          // segments of pass p: [item_begin[p], item_begin[p + 1])
+    long long tile_begin[4];    // tickets of pass p: [tile_begin[p], tile_begin[p + 1])
+    unsigned *counters;         // [0]: next ticket; [1 + i]: tiles of segment i done
+    unsigned *status;           // set to 1 if a wait ran past its bound
+    const void *in;
+    void *out;
+    unsigned spin_limit;        // polls before a wait gives up
+};
+
+constexpr int kBatchLengths[8] = {48, 60, 64, 72, 80, 96, 100, 128};
+constexpr int batch_threads(int n) { return (n == 64 || n == 128) ? 8 : 4; }
+
+template <int N, int KIND, class St>
+using BCfg = SCfg<N, KIND, (int)sizeof(typename St::Raw), (int)sizeof(cx<typename St::R>), N / batch_threads(N),
+                  256 / batch_threads(N), 0, 0>;
+
+template <class Cfg, class St, int KIND, bool INV>
+__device__ __forceinline__ void batch_tile(const PassArgs &a, long long tile, unsigned char *smem) {
+    using R = typename St::R;
+    static_assert(Cfg::kBlock == 256, "batched configurations use 256 threads");
+    constexpr int T = Cfg::T;
+    constexpr int L = Cfg::L;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
+    unsigned *red = nullptr;
+    const int tid = threadIdx.x;
+    const int l = KIND == kContiguous ? tid / T : tid % L;
+    const int t = KIND == kContiguous ? tid % T : tid / L;
+    if constexpr (Cfg::kTwN > 0) {
+        const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
+        for (int i = tid; i < Cfg::kTwN; i += Cfg::kBlock) tws[i] = W[tw_source<Cfg>(i)];
+        __syncthreads();
+    }
+    const long long es = KIND == kContiguous ? 1 : a.es;
+    const long long tx = KIND == kContiguous ? tile : tile % a.ntiles;
+    const long long w = KIND == kContiguous ? 0 : tile / a.ntiles;
+    const TileCoord c = tile_coord<Cfg, KIND>(a, tx, w, l);
+    const unsigned lane = lane_offset<Cfg, St, KIND>(l, t, es);
+    Tile<Cfg, St> cur;
+    fetch_tile<Cfg, St, KIND, INV>(a, c, t, lane, es, cur);
+    int ex = 0;
+    static_stage<Cfg, St, KIND, INV, 0>(a, lds, tws, red, t, l, c, lane, es, cur, ex);
+}
+
+template <class St, bool INV>
+__device__ __forceinline__ void batch_dispatch(const BatchItem &it, long long lt, const void *in, void *out,
+                                               unsigned char *smem) {
+    const size_t eb = sizeof(typename St::Raw);
+    PassArgs a;
+    a.in = reinterpret_cast<const char *>(it.from_in ? in : out) + it.offset * eb;
+    a.out = reinterpret_cast<char *>(out) + it.offset * eb;
+    a.tw = it.tw;
+    a.in_exp = nullptr;
+    a.out_exp = nullptr;
+    a.nlines = it.nlines;
+    a.es = it.es;
+    a.nw = it.nw;
+    a.ntiles = it.ntiles;
+    a.total = it.total;
+    a.inverse = INV;
+    switch (it.code) {
+#define CROFT_BATCH_CASE(I)                                                                                   \
+    case 2 * I: batch_tile<BCfg<kBatchLengths[I], kContiguous, St>, St, kContiguous, INV>(a, lt, smem); break; \
+    case 2 * I + 1: batch_tile<BCfg<kBatchLengths[I], kStrided, St>, St, kStrided, INV>(a, lt, smem); break;
+        CROFT_BATCH_CASE(0)
+        CROFT_BATCH_CASE(1)
+        CROFT_BATCH_CASE(2)
+        CROFT_BATCH_CASE(3)
+        CROFT_BATCH_CASE(4)
+        CROFT_BATCH_CASE(5)
+        CROFT_BATCH_CASE(6)
+        CROFT_BATCH_CASE(7)
+#undef CROFT_BATCH_CASE
+        default: break;
+    }
+}
+
+__device__ __forceinline__ int find_segment(const BatchItem *items, int lo, int hi, long long tile) {
+    // last segment in [lo, hi] whose first tile is <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (items[mid].tile_begin <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class St, bool INV>
+__global__ void __launch_bounds__(256) fft_batch_persistent(const BatchPersistentArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_ticket;
+    const long long total = b.tile_begin[3];
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(&b.counters[0], 1u);
+        __syncthreads();
+        const long long ticket = s_ticket;
+        if (ticket >= total) break;  // uniform: every block leaves once the tickets run out
+        const int p = ticket < b.tile_begin[1] ? 0 : (ticket < b.tile_begin[2] ? 1 : 2);
+        const long long pt = ticket - b.tile_begin[p];
+        const int si = find_segment(b.items, b.item_begin[p], b.item_begin[p + 1] - 1, pt);
+        const BatchItem it = b.items[si];
+        if (it.dep >= 0) {
+            if (threadIdx.x == 0) {
+                unsigned polls = 0;
+                while (__hip_atomic_load(&b.counters[1 + it.dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                       (unsigned)it.dep_total) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++polls >= b.spin_limit) {
+                        atomicOr(b.status, 1u);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        batch_dispatch<St, INV>(it, pt - it.tile_begin, b.in, b.out, smem);
+        // every thread's stores of this tile are ordered before the count
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&b.counters[1 + si], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <class St, bool INV>
+__global__ void __launch_bounds__(256) fft_batch(const BatchArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const long long tile = blockIdx.x;
+    const BatchItem it = b.items[find_segment(b.items, 0, b.nitems - 1, tile)];
+    batch_dispatch<St, INV>(it, tile - it.tile_begin, b.in, b.out, smem);
+}
+
 // ------------------------------------------------------------ kernel table
 struct Entry {
     int n, kind, dtype, cand;

@@ -86,6 +86,31 @@ long long pass_tiles(const PassLaunch &pl);
 hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *out,
                        const int8_t *in_exp, int8_t *out_exp, int inverse, hipStream_t stream);
 
+// ---- batched form (croft_batch.hip) ----
+struct BatchConfig {
+    int n = 0, kind = 0, threads_per_line = 0, lines = 0;
+    size_t lds = 0;
+};
+// Code of a (length, kind) the batched kernel compiles, -1 if none.
+int batch_code(int n, int kind);
+bool batch_config(int code, int dtype, BatchConfig *c);
+const void *batch_kernel(int dtype, int inverse);
+size_t batch_item_bytes();
+void batch_item_fill(void *dst, long long offset, long long tile_begin, long long es, long long nlines,
+                     long long nw, long long ntiles, long long total, const void *tw, int code, int from_in,
+                     int dep, long long dep_total);
+const void *batch_persistent_kernel(int dtype, int inverse);
+// Zero the counters, then one persistent launch of `blocks` blocks over every
+// pass of every grid in the table (segments of pass p at
+// [item_begin[p], item_begin[p+1]), tickets [tile_begin[p], tile_begin[p+1])).
+hipError_t launch_batch_persistent(const void *items, const int item_begin[4], const long long tile_begin[4],
+                                   unsigned *counters, unsigned ncounters, unsigned *status, int blocks,
+                                   size_t lds, int dtype, int inverse, const void *in, void *out,
+                                   hipStream_t stream);
+// One launch over `tiles` tiles described by the device array `items`.
+hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t lds, int dtype, int inverse,
+                        const void *in, void *out, hipStream_t stream);
+
 // ---- wisdom (croft_tune.cpp) ----
 bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves);
 void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist);
