@@ -5,13 +5,15 @@ three axis passes with their in-LDS transposes) on a PME-style charge grid
 already resident in HBM; `value` is GFLOP/s by the 5 N log2 N convention.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--size 512] [--slabs K]
-                  [--no-cpu-baseline] [--forms] [--calibrate-copy]
+                  [--no-cpu-baseline] [--no-forms] [--calibrate-copy]
 
 The dominant kernel's roofline uses HIP events recorded by the library around
 each pass launch on the stream the pass runs on, over the timed region.
 `--calibrate-copy` instead times a plain device copy of the same bytes (used
-to scale the HBM byte counters); `--forms` adds the half-storage, batched and
-other measured forms to the line.
+to scale the HBM byte counters).  The line also carries the half-storage
+(FP16, BF16 at 512^3) and batched (64 uneven grids) forms, each timed next to
+the plain complex64 form on the same GPU with its error against it
+(`--no-forms` skips them).
 """
 from __future__ import annotations
 
@@ -54,7 +56,7 @@ def parse():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--slabs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
 
@@ -122,13 +124,20 @@ def time_plan(torch, croft, plan, fn, steps, warmup, npasses):
     return ms, [m / max(n, 1) for m in pass_ms[:npasses]], wall
 
 
+def rel_l2_dev(torch, a, b) -> float:
+    """||a - b|| / ||b|| over complex128 views, on the device."""
+    a = a.to(torch.complex128)
+    b = b.to(torch.complex128)
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
 def measure_forms(torch, np, croft, synth, steps):
-    """Half-storage (512^3), batched (64 uneven grids) and inverse forms, each
-    next to the plain FP32 form on the same GPU."""
+    """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
+    next to the plain complex64 form on the same input and GPU, with its error
+    against that form."""
     out = {}
     n = 512
     N = n ** 3
-    # half storage at 512^3 from N(0,1) inputs quantised on the host
     v = synth.normal_c((n, n, n), seed=5)
     for name, dt, kind in (("c16f", croft.CROFT_C16F, "f16"), ("c16b", croft.CROFT_C16B, "bf16")):
         data, e = synth.quantize_half(v, kind)
@@ -143,9 +152,21 @@ def measure_forms(torch, np, croft, synth, steps):
                               steps, 3, 3)
         info = croft.croft_plan_info(plan)
         croft.croft_plan_destroy(plan)
+        # the plain complex64 form on the stored input's exact values
+        vals = (d_in.float()[..., 0] + 1j * d_in.float()[..., 1]).to(torch.complex64)
+        vals = vals * torch.pow(2.0, e_in.float())[:, :, None]
+        c_out = torch.empty_like(vals)
+        cplan = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+        ms_c64, _, _ = time_plan(torch, croft, cplan, lambda: croft.croft_execute(cplan, vals, c_out),
+                                 steps, 3, 3)
+        croft.croft_plan_destroy(cplan)
+        got = (d_out.float()[..., 0] + 1j * d_out.float()[..., 1]) * torch.pow(2.0, e_out.float())[None, :, :]
+        err = rel_l2_dev(torch, got, c_out)
         out[name] = {"ms": ms, "GFLOPs": flops_5nlogn(N) / ms / 1e6,
-                     "effective_GBps": info["algorithmic_bytes"] / ms / 1e6, "pass_ms": pm}
-        del d_in, d_out
+                     "effective_GBps": info["algorithmic_bytes"] / ms / 1e6, "pass_ms": pm,
+                     "c64_ms": ms_c64, "speedup_vs_c64": ms_c64 / ms, "rel_l2_vs_c64": err}
+        del d_in, d_out, vals, c_out, got
+        torch.cuda.empty_cache()
     del v
     # batched: 64 uneven PME grids
     dims = synth.batch_dims(4)
@@ -172,7 +193,8 @@ def measure_forms(torch, np, croft, synth, steps):
     plans = [croft.croft_plan_create(int(a), int(b), int(c), croft.CROFT_C64, croft.CROFT_FORWARD)
              for a, b, c in dims]
     offs = np.concatenate([[0], np.cumsum([g.size for g in grids])])
-    views = [(d_in[offs[i]:offs[i + 1]], d_out[offs[i]:offs[i + 1]]) for i in range(len(grids))]
+    ref = torch.empty_like(d_in)
+    views = [(d_in[offs[i]:offs[i + 1]], ref[offs[i]:offs[i + 1]]) for i in range(len(grids))]
 
     def plain_all():
         for p, (i_, o_) in zip(plans, views):
@@ -190,7 +212,8 @@ def measure_forms(torch, np, croft, synth, steps):
         croft.croft_plan_destroy(p)
     out["batched_64"] = {"ms": ms, "GFLOPs": fl / ms / 1e6, "elements": int(flat.size),
                          "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
-                         "plain_calls_ms": ms_plain}
+                         "plain_calls_ms": ms_plain, "speedup_vs_plain_calls": ms_plain / ms,
+                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref))}
     return out
 
 
@@ -256,7 +279,7 @@ def main():
                      "bytes_per_launch": per_launch, "avg_launch_ms": pass_ms[dom]},
         "check": {"dc": [dc.real, dc.imag], "total_charge": qtot},
     }
-    if args.forms:
+    if not args.no_forms:
         del d_in, d_out
         torch.cuda.empty_cache()
         line["forms"] = measure_forms(torch, np, croft, synth, max(10, args.steps // 2))

@@ -10,20 +10,22 @@ namespace dev {
 
 #define DEF(N) make_entry<N, kContiguous, StC64, 8, kC64>(0), make_entry<N, kStrided, StC64, 8, kC64>(0)
 // contiguous: 1 padded LDS lines, 2 no prefetch;
-// strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch
-#define CAND(N, EW, LW)                                                          \
+// strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
+// 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines)
+#define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 0, 0>(2),             \
         make_entry<N, kStrided, StC64, 8, kC64, 0, 0, 0, 0>(1),                \
         make_entry<N, kStrided, StC64, 8, kC64, EW, LW, 0, 0>(2),              \
-        make_entry<N, kStrided, StC64, 8, kC64, EW, LW, 0, 1>(3)
+        make_entry<N, kStrided, StC64, 8, kC64, EW, LW, 0, 1>(3),              \
+        make_entry<N, kStrided, StC64, 8, kC64, EW2, LW2, 0, 0>(4)
 
 std::vector<Entry> entries_c64() {
     return {
         DEF(2),   DEF(4),   DEF(8),   DEF(16),   DEF(32),   DEF(64),   DEF(128),
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384),
-        CAND(128, 16, 32), CAND(256, 16, 32), CAND(512, 16, 32), CAND(1024, 32, 16),
+        CAND(128, 16, 32, 32, 32), CAND(256, 16, 32, 32, 32), CAND(512, 16, 32, 32, 32), CAND(1024, 32, 16, 64, 16),
     };
 }
 

@@ -27,9 +27,9 @@ const Builtin kBuiltin[] = {
     // complex64
     {512, 0, 0, 1, 0}, {512, 1, 0, 2, 4}, {256, 0, 0, 1, 0}, {256, 1, 0, 1, 0}, {128, 0, 0, 1, 0},
     // complex128
-    {512, 0, 1, 1, 0}, {512, 1, 1, 2, 2}, {256, 1, 1, 2, 0},
+    {512, 0, 1, 0, 0}, {512, 1, 1, 2, 4}, {256, 1, 1, 2, 0},
     // FP16 / BF16 storage
-    {512, 0, 2, 2, 4}, {512, 1, 2, 1, 2}, {512, 0, 3, 2, 4}, {512, 1, 3, 1, 2},
+    {512, 0, 2, 2, 4}, {512, 1, 2, 4, 2}, {512, 0, 3, 2, 4}, {512, 1, 3, 4, 2},
 };
 
 std::mutex g_mu;
