@@ -124,3 +124,46 @@ def test_describe_launch_shapes_fit_the_device():
                 assert int(p["block"]) <= 1024 and int(p["block"]) % 1 == 0
                 assert int(p["lds"]) <= 160 * 1024
                 assert int(p["T"]) * int(p["L"]) <= int(p["block"])
+
+
+def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
+    w = tmp_path / "wisdom.txt"
+    w.write_text(text)
+    monkeypatch.setenv("CROFT_WISDOM", str(w))
+    return parse_describe(croft.croft_plan_describe(*args))[1]
+
+
+def test_builtin_wisdom_picks_wide_strided_tiles(tmp_path, monkeypatch):
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512)
+    assert [p["candidate"] for p in passes] == ["1", "2", "2"]
+    assert passes[1]["L"] == "32" and passes[1]["T"] == "32" and passes[1]["waves"] == "4"
+
+
+def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 0 1\n512 0 0 2 3\n", 512, 512, 512)
+    assert passes[0]["candidate"] == "2" and passes[0]["waves"] == "3"
+    assert passes[1]["candidate"] == "0" and passes[1]["L"] == "16" and passes[1]["waves"] == "1"
+    # the last matching line wins
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 0 1\n512 1 0 4 2\n", 512, 512, 512)
+    assert passes[2]["candidate"] == "4" and passes[2]["block"] == "512"
+
+
+def test_wisdom_unknown_candidate_falls_back_to_default(tmp_path, monkeypatch):
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 9 1\n", 512, 512, 512)
+    assert passes[1]["candidate"] == "0"
+
+
+def test_wisdom_does_not_affect_generic_lengths(tmp_path, monkeypatch):
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "45 0 0 2 2\n", 45, 8, 8)
+    assert passes[0]["kernel"] == "generic"
+
+
+def test_every_candidate_fits_the_device(tmp_path, monkeypatch):
+    for n in (128, 256, 512, 1024):
+        for dt in range(4):
+            for kind in (0, 1):
+                for cand in range(5):
+                    passes = _describe_with_wisdom(tmp_path, monkeypatch, f"{n} {kind} {dt} {cand} 1\n",
+                                                   n, n if kind else 2, 4, dt)
+                    for p in passes:
+                        assert int(p["block"]) <= 1024 and int(p["lds"]) <= 160 * 1024
