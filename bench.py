@@ -131,6 +131,42 @@ def rel_l2_dev(torch, a, b) -> float:
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
+def measure_real(torch, np, croft, pme, steps):
+    """Real forward (real grid -> half spectrum) and backward transforms of the
+    PME grid, timed next to the complex64 transform of the same grid, with the
+    error of the half spectrum against that transform's first half and the
+    round-trip error."""
+    n = pme.shape[0]
+    N = n ** 3
+    d_c = torch.from_numpy(pme).cuda()
+    d_cy = torch.empty_like(d_c)
+    cplan = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+    ms_c64, _, _ = time_plan(torch, croft, cplan, lambda: croft.croft_execute(cplan, d_c, d_cy), steps, 3, 3)
+    croft.croft_plan_destroy(cplan)
+    d_x = d_c.real.contiguous()
+    del d_c
+    d_h = torch.empty((n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    d_back = torch.empty_like(d_x)
+    out = {}
+    for name, direction, src, dst in (("real_forward", croft.CROFT_FORWARD, d_x, d_h),
+                                      ("real_backward", croft.CROFT_BACKWARD, d_h, d_back)):
+        plan = croft.croft_plan_create_real(n, n, n, croft.CROFT_C64, direction, 0)
+        info = croft.croft_plan_info(plan)
+        ms, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, src, dst), steps, 3,
+                              info["npasses"])
+        croft.croft_plan_destroy(plan)
+        out[name] = {"ms": ms, "GFLOPs_2.5NlogN": info["flops"] / ms / 1e6,
+                     "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
+                     "algorithmic_bytes": info["algorithmic_bytes"], "pass_ms": pm,
+                     "c2c_c64_ms": ms_c64, "speedup_vs_c2c": ms_c64 / ms}
+    out["real_forward"]["rel_l2_vs_c2c_half"] = rel_l2_dev(torch, d_h, d_cy[:, :, : n // 2 + 1])
+    out["real_backward"]["round_trip_rel_l2"] = rel_l2_dev(torch, (d_back / N).to(torch.complex64),
+                                                           d_x.to(torch.complex64))
+    del d_x, d_h, d_back, d_cy
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_forms(torch, np, croft, synth, steps):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
@@ -282,7 +318,8 @@ def main():
     if not args.no_forms:
         del d_in, d_out
         torch.cuda.empty_cache()
-        line["forms"] = measure_forms(torch, np, croft, synth, max(10, args.steps // 2))
+        line["forms"] = measure_real(torch, np, croft, x, max(10, args.steps // 2))
+        line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2)))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, n)
     print(json.dumps(line))

@@ -110,7 +110,8 @@ croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, in
 
 /* Run the transform of a C64/C128 plan.  in == out runs in place; otherwise
  * the buffers must not overlap and `in` is left unchanged.  Each buffer holds
- * nx*ny*nz elements of the plan's dtype.  Asynchronous on `stream`. */
+ * nx*ny*nz elements of the plan's dtype (real plans: the layouts given at
+ * croft_plan_create_real).  Asynchronous on `stream`. */
 int croft_execute(croft_plan_t plan, const void *in, void *out, hipStream_t stream);
 
 /* Run the transform of a C16F/C16B plan.  Values are stored * 2^exp.
@@ -142,13 +143,41 @@ croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, in
  * being the total element count.  `elem_offsets` is host memory. */
 int croft_plan_batched_offsets(croft_plan_t plan, size_t *elem_offsets);
 
-/* Run every transform of a batched plan: one launch per axis pass covering
+/* Run every transform of a batched plan (one from croft_plan_create_batched;
+ * others give CROFT_ERR_INVALID_VALUE): one launch per axis pass covering
  * all grids (or one persistent launch with CROFT_PERSISTENT), replayed from a
  * HIP graph captured on first use for the given (in, out, stream).  Grids
  * whose lengths the batched kernels do not compile (any outside 48, 60, 64,
  * 72, 80, 96, 100, 128) run with launches of their own inside the same graph.
  * Same in/out rules as croft_execute. */
 int croft_execute_batched(croft_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/* Real transforms (Section 1: PME transforms a real charge grid forward and
+ * brings the reciprocal-space result back to a real grid; the spectrum of a
+ * real grid is Hermitian, Y(-k) = conj Y(k), so the kx = 0..nx/2 half of
+ * Eq. (1)'s output determines the rest).  dtype CROFT_C64 (float reals,
+ * complex float spectrum, FP32 compute) or CROFT_C128 (double, FP64).
+ * nx even, 4 <= nx <= 8192, with nx/2 among the lengths the library compiles
+ * (powers of two 2..4096 and 48, 60, 72, 80, 96, 100, 384); ny and nz as for
+ * croft_plan_create.  flags: CROFT_MEASURE, CROFT_FORCE_GENERIC (y and z
+ * passes only), CROFT_NO_WISDOM.  Returns NULL on failure.
+ * Layouts, run with croft_execute (out of place only: overlapping in and out
+ * give CROFT_ERR_INVALID_VALUE; `in` is left unchanged):
+ *   real grid:     nx*ny*nz reals, element (x, y, z) at x + nx*(y + ny*z)
+ *   half spectrum: (nx/2+1)*ny*nz complex, (kx, ky, kz) at
+ *                  kx + (nx/2+1)*(ky + ny*kz), kx = 0..nx/2
+ *   CROFT_FORWARD:  real grid -> Y(kx, ky, kz) of Eq. (1), kx <= nx/2.
+ *   CROFT_BACKWARD: half spectrum -> real grid: the unnormalised inverse of
+ *                   Eq. (2) over z and y, then along x the real inverse of
+ *                   the Hermitian extension in kx, which uses only the real
+ *                   parts of the kx = 0 and kx = nx/2 terms
+ *                   x(n) = Re H(0) + (-1)^n Re H(nx/2)
+ *                          + 2 Re sum_{0<k<nx/2} H(k) exp(2 pi i k n / nx).
+ *                   For the spectrum of a real grid this is nx*ny*nz times
+ *                   that grid (no 1/N factor, as for complex plans).
+ * A backward plan with ny*nz > 1 owns a work buffer of one half spectrum
+ * (counted in croft_plan_info.work_bytes). */
+croft_plan_t croft_plan_create_real(int nx, int ny, int nz, int dtype, int dir, int flags);
 
 /* Waits for the device and reports whether a persistent batched launch of
  * this plan ever had to give up waiting for a previous pass (device_status
@@ -163,7 +192,7 @@ int croft_plan_status(croft_plan_t plan, int *device_status);
 struct croft_pass_info {
     int axis;            /* 0 = x, 1 = y, 2 = z */
     int n;               /* transform length */
-    int kind;            /* 0: contiguous lines, 1: strided lines */
+    int kind;            /* 0: contiguous lines, 1: strided lines, 2: real x pass (n = nx/2) */
     int generic;         /* 1 if the runtime-radix kernel runs this pass */
     int nstages;
     int radices[CROFT_MAX_STAGES];
@@ -182,8 +211,11 @@ struct croft_plan_info {
     size_t elements;          /* total elements (all grids for a batched plan) */
     size_t element_bytes;     /* bytes per stored element */
     size_t work_bytes;        /* device scratch owned by the plan */
-    double algorithmic_bytes; /* 3 sweeps x (read + write) x elements x element_bytes */
-    double flops;             /* sum over grids of 5 N log2 N */
+    double algorithmic_bytes; /* 3 sweeps x (read + write) x elements x element_bytes; real
+                                 plans: real grid + half spectrum for the x pass, twice the
+                                 half spectrum for each of the others */
+    double flops;             /* sum over grids of 5 N log2 N (real plans: 2.5 N log2 N) */
+    int real;                 /* 1 for a plan of croft_plan_create_real */
 };
 int croft_plan_info(croft_plan_t plan, struct croft_plan_info *info);
 
@@ -191,6 +223,9 @@ int croft_plan_info(croft_plan_t plan, struct croft_plan_info *info);
  * build (passes, radices, launch shapes, bytes) into buf (len bytes, always
  * NUL-terminated when len > 0).  Uses no GPU.  Returns a croft_status. */
 int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len);
+
+/* The same dry run for the plan croft_plan_create_real would build. */
+int croft_plan_describe_real(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len);
 
 /* Per-kernel timing: while enabled, every execute on the plan records HIP
  * events around each pass launch on the stream it is launched on.

@@ -14,6 +14,13 @@ What it computes (the paper, Section 2.1):
 * ``dft3d_lines``        -- exact output lines of large grids.
 * ``dft_axis_lines``     -- the 1D transform of a range of lines along one axis
   (the building block of ``dft3d``; used to time a bounded sample).
+* ``rdft3d``             -- forward transform of a real grid: Eq. (1) for
+  kx = 0..nx/2 (the rest is fixed by Hermitian symmetry); ``rdft3d_lines``
+  gives exact half-spectrum lines of large grids.
+* ``irdft3d``            -- backward transform of a half spectrum to a real
+  grid: the unnormalised backward sum over z and y, then the real inverse
+  of the Hermitian extension along x (``c2r_x``); ``irdft3d_lines`` gives
+  exact real output lines of large grids (``yz_sums`` + ``c2r_x``).
 * ``decode_half``        -- the exact value of FP16/BF16 storage with per-line
   power-of-two exponents (value = stored * 2**e).
 * ``rel_l2``             -- the error metric ||a - ref||_2 / ||ref||_2.
@@ -73,6 +80,8 @@ def bind(path: str):
     lib.oracle_dft3d_brute.restype = i
     lib.oracle_dft3d_lines.argtypes = [i, i, i, p, i, i, p, p, p]
     lib.oracle_dft3d_lines.restype = i
+    lib.oracle_yz_sums.argtypes = [i, i, i, p, i, i, p, p, p]
+    lib.oracle_yz_sums.restype = i
     return lib
 
 
@@ -138,6 +147,21 @@ class Oracle:
             raise ValueError("oracle_dft3d_lines failed")
         return out
 
+    def yz_sums(self, x, kyz, sign: int = FORWARD) -> np.ndarray:
+        """For each (ky, kz) in ``kyz`` and every x: the y and z sums of the
+        transform with the given sign, before any sum over x: (len(kyz), nx)."""
+        a = self._grid(x)
+        nz, ny, nx = a.shape
+        kyz = np.asarray(kyz, dtype=np.int32).reshape(-1, 2)
+        ky = np.ascontiguousarray(kyz[:, 0])
+        kz = np.ascontiguousarray(kyz[:, 1])
+        out = np.empty((len(kyz), nx), dtype=np.complex128)
+        rc = self.lib.oracle_yz_sums(nx, ny, nz, a.ctypes.data, sign, len(kyz),
+                                     ky.ctypes.data, kz.ctypes.data, out.ctypes.data)
+        if rc != 0:
+            raise ValueError("oracle_yz_sums failed")
+        return out
+
     def dft_axis_lines(self, a: np.ndarray, axis: int, first: int, count: int,
                        sign: int = FORWARD) -> None:
         """In place on a C-contiguous complex128 (nz, ny, nx) array."""
@@ -182,6 +206,69 @@ def dft3d_lines(x, kyz, sign: int = FORWARD) -> np.ndarray:
 
 def dft_axis_lines(a, axis, first, count, sign: int = FORWARD) -> None:
     _o().dft_axis_lines(a, axis, first, count, sign)
+
+
+def yz_sums(x, kyz, sign: int = FORWARD) -> np.ndarray:
+    return _o().yz_sums(x, kyz, sign)
+
+
+# ------------------------------------------------------------ real transforms
+# The PME charge grid of Section 1 is real; the spectrum of a real grid obeys
+# Y(-k) = conj Y(k) under Eq. (1), so its kx = 0..nx/2 half holds everything.
+
+def rdft3d(x) -> np.ndarray:
+    """Eq. (1) of a real (nz, ny, nx) grid, kept for kx = 0..nx/2:
+    shape (nz, ny, nx//2 + 1)."""
+    a = np.asarray(x, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("expected a real (nz, ny, nx) array")
+    return np.ascontiguousarray(dft3d(a.astype(np.complex128), FORWARD)[:, :, : a.shape[2] // 2 + 1])
+
+
+def rdft3d_lines(x, kyz) -> np.ndarray:
+    """Half-spectrum lines Y(0..nx/2, ky, kz) of a real grid: (len(kyz), nx//2 + 1)."""
+    a = np.asarray(x, dtype=np.float64)
+    return dft3d_lines(a.astype(np.complex128), kyz, FORWARD)[:, : a.shape[2] // 2 + 1]
+
+
+def c2r_x(g, nx: int) -> np.ndarray:
+    """Real inverse along x of half-spectrum lines g[..., 0..nx/2] (nx even),
+    unnormalised: the sum over kx = 0..nx-1 of the Hermitian extension
+    G(nx - k) = conj G(k), times exp(+2 pi i k n / nx).  Written out, with
+    m = nx/2 (the imaginary parts of G(0) and G(m) drop out of the sum):
+        x(n) = Re G(0) + (-1)^n Re G(m) + 2 Re sum_{0<k<m} G(k) exp(2 pi i k n / nx).
+    """
+    g = np.asarray(g, dtype=np.complex128)
+    if nx % 2 or g.shape[-1] != nx // 2 + 1:
+        raise ValueError("need nx even and nx//2 + 1 values per line")
+    m = nx // 2
+    n = np.arange(nx)
+    k = np.arange(1, m)
+    phase = 2.0 * np.pi * ((k[:, None] * n[None, :]) % nx) / nx   # exact k n mod nx
+    e = np.cos(phase) + 1j * np.sin(phase)
+    sign_n = np.where(n % 2 == 0, 1.0, -1.0)
+    inner = g[..., 1:m] @ e if m > 1 else np.zeros(g.shape[:-1] + (nx,), np.complex128)
+    return g[..., :1].real + sign_n * g[..., m:m + 1].real + 2.0 * inner.real
+
+
+def irdft3d(h, nx: int) -> np.ndarray:
+    """Backward transform of a half spectrum h (nz, ny, nx//2 + 1) to a real
+    (nz, ny, nx) grid, without Eq. (2)'s 1/N: the backward sums along z and y
+    (sign +1), then ``c2r_x`` along x.  For the half spectrum of a real grid
+    this is N times that grid."""
+    a = np.ascontiguousarray(np.asarray(h), dtype=np.complex128).copy()
+    if a.ndim != 3:
+        raise ValueError("expected a (nz, ny, nx//2 + 1) array")
+    nz, ny, hx = a.shape
+    dft_axis_lines(a, 1, 0, hx * nz, BACKWARD)
+    dft_axis_lines(a, 2, 0, hx * ny, BACKWARD)
+    return c2r_x(a, nx)
+
+
+def irdft3d_lines(h, nx: int, yz) -> np.ndarray:
+    """Real output lines x(0..nx-1, y, z) of ``irdft3d`` for each (y, z) in
+    ``yz``: (len(yz), nx)."""
+    return c2r_x(yz_sums(h, yz, BACKWARD), nx)
 
 
 def backward_eq2(y) -> np.ndarray:

@@ -160,30 +160,25 @@ int oracle_dft3d_brute(int nx, int ny, int nz, const double *in, double *out, in
     return 0;
 }
 
-/* Exact output lines of a large grid: for each of the `nsamp` pairs
- * (ky[i], kz[i]) it writes the nx values Y(kx, ky[i], kz[i]), kx = 0..nx-1,
- * to out[i*nx + kx] (interleaved complex).  By Eq. (1),
- *   Y(kx,ky,kz) = sum_x e_x(kx x) * [ sum_z e_z(kz z) sum_y e_y(ky y) X(x,y,z) ]
- * where e_a(m) = exp(sign 2 pi i m / Na).  The bracket is an O(N) reduction
- * that yields one value per x; a naive DFT over x then gives the line.
- * `in` is not modified. */
-int oracle_dft3d_lines(int nx, int ny, int nz, const double *in, int sign,
-                       int nsamp, const int *ky, const int *kz, double *out)
+/* The inner O(N) reduction of an exact output line: for each of the `nsamp`
+ * pairs (ky[i], kz[i]) it writes, for every x,
+ *   red[i*nx + x] = sum_z e_z(kz z) sum_y e_y(ky y) X(x,y,z)
+ * (interleaved complex), e_a(m) = exp(sign 2 pi i m / Na) -- the y and z sums
+ * of Eq. (1) (sign -1) or of Eq. (2) without 1/N (sign +1), done before any
+ * sum over x.  Parallel over (i, block of XB consecutive x); the x loop is
+ * innermost so rows are read contiguously.  For each x the sums run in the
+ * order written above.  `in` is not modified. */
+int oracle_yz_sums(int nx, int ny, int nz, const double *in, int sign,
+                   int nsamp, const int *ky, const int *kz, double *red)
 {
     if (nx < 1 || ny < 1 || nz < 1 || (sign != 1 && sign != -1) || nsamp < 0) return -1;
     for (int i = 0; i < nsamp; ++i)
         if (ky[i] < 0 || ky[i] >= ny || kz[i] < 0 || kz[i] >= nz) return -1;
-    double *tx = (double *)malloc(sizeof(double) * 2 * (size_t)nx);
     double *ty = (double *)malloc(sizeof(double) * 2 * (size_t)ny);
     double *tz = (double *)malloc(sizeof(double) * 2 * (size_t)nz);
-    double *red = (double *)malloc(sizeof(double) * 2 * (size_t)nx * (size_t)nsamp);
-    if (!tx || !ty || !tz || !red) { free(tx); free(ty); free(tz); free(red); return -1; }
-    make_table(nx, tx, tx + nx);
+    if (!ty || !tz) { free(ty); free(tz); return -1; }
     make_table(ny, ty, ty + ny);
     make_table(nz, tz, tz + nz);
-    /* red[i][x] = sum_z e_z(kz z) sum_y e_y(ky y) X(x,y,z), parallel over
-     * (i, block of XB consecutive x); the x loop is innermost so rows are read
-     * contiguously.  For each x the sums run in the order written above. */
     enum { XB = 64 };
     const int nxb = (nx + XB - 1) / XB;
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
@@ -220,6 +215,26 @@ int oracle_dft3d_lines(int nx, int ny, int nz, const double *in, int sign,
             }
         }
     }
+    free(ty); free(tz);
+    return 0;
+}
+
+/* Exact output lines of a large grid: for each of the `nsamp` pairs
+ * (ky[i], kz[i]) it writes the nx values Y(kx, ky[i], kz[i]), kx = 0..nx-1,
+ * to out[i*nx + kx] (interleaved complex).  By Eq. (1),
+ *   Y(kx,ky,kz) = sum_x e_x(kx x) * [ sum_z e_z(kz z) sum_y e_y(ky y) X(x,y,z) ]
+ * where e_a(m) = exp(sign 2 pi i m / Na).  The bracket is the O(N) reduction
+ * of oracle_yz_sums, one value per x; a naive DFT over x then gives the line.
+ * `in` is not modified. */
+int oracle_dft3d_lines(int nx, int ny, int nz, const double *in, int sign,
+                       int nsamp, const int *ky, const int *kz, double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || (sign != 1 && sign != -1) || nsamp < 0) return -1;
+    double *tx = (double *)malloc(sizeof(double) * 2 * (size_t)nx);
+    double *red = (double *)malloc(sizeof(double) * 2 * (size_t)nx * (size_t)(nsamp > 0 ? nsamp : 1));
+    if (!tx || !red) { free(tx); free(red); return -1; }
+    make_table(nx, tx, tx + nx);
+    if (oracle_yz_sums(nx, ny, nz, in, sign, nsamp, ky, kz, red)) { free(tx); free(red); return -1; }
     for (int i = 0; i < nsamp; ++i) {
         for (int kx = 0; kx < nx; ++kx) {
             double ar = 0.0, ai = 0.0;
@@ -236,6 +251,6 @@ int oracle_dft3d_lines(int nx, int ny, int nz, const double *in, int sign,
             out[2 * ((long)i * nx + kx) + 1] = ai;
         }
     }
-    free(tx); free(ty); free(tz); free(red);
+    free(tx); free(red);
     return 0;
 }

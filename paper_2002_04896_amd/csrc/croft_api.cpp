@@ -50,6 +50,10 @@ struct croft_plan {
     std::map<int, void *> twiddles;  // length -> device table
     int8_t *e1 = nullptr, *e2 = nullptr;  // half storage: exponents after x and y passes
     size_t work_bytes = 0;
+    // real transforms: grids[0] holds the real dimensions; the backward
+    // direction runs its complex passes in `rwork` (the input is kept)
+    bool real = false;
+    void *rwork = nullptr;
     // slab schedule
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
@@ -168,6 +172,65 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
     return CROFT_SUCCESS;
 }
 
+// The pass list of a real transform of an nx x ny x nz real grid (nx even):
+// the real x pass on the half-length complex view, and the complex y and z
+// passes on the (nx/2 + 1) x ny x nz half spectrum.  Forward runs x, y, z;
+// backward z, y, x.
+int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<PassLaunch> *out) {
+    out->clear();
+    const int m = g.nx / 2;
+    const long long h = (long long)m + 1;  // spectrum elements per x-line
+    PassLaunch xp;
+    xp.axis = 0;
+    xp.n = m;
+    xp.kind = kRealX;
+    xp.es = 1;
+    xp.nlines = (long long)g.ny * g.nz;
+    int cand = 0, waves = 1;
+    wisdom_lookup(m, kRealX, dtype, &cand, &waves);
+    if (!select_kernel(m, kRealX, dtype, false, cand, &xp.cfg))
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no real x kernel for nx = %d (half length %d)", g.nx, m);
+    xp.cfg.grid_waves = waves;
+    std::vector<PassLaunch> yz;
+    for (int axis = 1; axis < 3; ++axis) {
+        const int n = axis == 1 ? g.ny : g.nz;
+        if (n == 1) continue;
+        PassLaunch p;
+        p.axis = axis;
+        p.n = n;
+        p.kind = kStrided;
+        p.es = axis == 1 ? h : h * g.ny;
+        p.nlines = p.es;
+        p.nw = axis == 1 ? g.nz : 1;
+        wisdom_lookup(n, kStrided, dtype, &cand, &waves);
+        if (!select_kernel(n, kStrided, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
+            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+        p.cfg.grid_waves = waves;
+        yz.push_back(p);
+    }
+    if (dir == CROFT_FORWARD) {
+        out->push_back(xp);
+        out->insert(out->end(), yz.begin(), yz.end());
+    } else {
+        out->insert(out->end(), yz.rbegin(), yz.rend());
+        out->push_back(xp);
+    }
+    return CROFT_SUCCESS;
+}
+
+int check_real_dims(int nx, int ny, int nz, int dtype) {
+    if (dtype != CROFT_C64 && dtype != CROFT_C128)
+        return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "real transforms take CROFT_C64 or CROFT_C128");
+    if (nx < 4 || nx % 2 != 0 || nx / 2 > kMaxLength)
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "real transforms need an even nx in 4..%d (got %d)",
+                    2 * kMaxLength, nx);
+    const int rc = check_dims(nx / 2, ny, nz);
+    if (rc != CROFT_SUCCESS) return rc;
+    if (((long long)nx / 2 + 1) * ny * nz > 0x7fffffffLL)
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "half spectrum exceeds 2^31 - 1 elements");
+    return CROFT_SUCCESS;
+}
+
 // Largest exponent index a pass touches (host-side bound check of ExpMap).
 void exp_extent(const PassLaunch &p, long long *in_max, long long *out_max) {
     const ExpMap &m = p.em;
@@ -206,6 +269,7 @@ void destroy_plan(croft_plan *p) {
     for (auto &kv : p->twiddles) (void)hipFree(kv.second);
     if (p->e1) (void)hipFree(p->e1);
     if (p->e2) (void)hipFree(p->e2);
+    if (p->rwork) (void)hipFree(p->rwork);
     for (int i = 0; i < 2; ++i) {
         if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
         if (p->join[i]) (void)hipEventDestroy(p->join[i]);
@@ -258,32 +322,48 @@ int prepare_kernel(KernelConfig *cfg) {
 int attach_resources(croft_plan *p) {
     hipError_t e;
     const bool dbl = p->dtype == CROFT_C128;
+    // the table w_n^m, m < n, of a length, uploaded once per plan
+    auto table = [&](int n, const void **out) -> int {
+        if (!p->twiddles.count(n)) {
+            std::vector<double> w(2 * (size_t)n);
+            twiddles_fp64(n, w.data());
+            void *d = nullptr;
+            const size_t bytes = (size_t)n * compute_bytes(p->dtype);
+            if ((e = hipMalloc(&d, bytes)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(CROFT_ERR_OUT_OF_MEMORY, "twiddle table: %s", hipGetErrorString(e));
+            }
+            p->twiddles[n] = d;
+            p->work_bytes += bytes;
+            if (dbl) {
+                e = hipMemcpy(d, w.data(), bytes, hipMemcpyHostToDevice);
+            } else {
+                std::vector<float> f(w.size());
+                for (size_t i = 0; i < w.size(); ++i) f[i] = (float)w[i];  // round to nearest even
+                e = hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice);
+            }
+            if (e != hipSuccess) return fail_hip(e, "twiddle upload");
+        }
+        *out = p->twiddles[n];
+        return CROFT_SUCCESS;
+    };
     for (auto &ps : p->passes) {
         for (PassLaunch &pl : ps) {
-            if (pl.n > 1 && !p->twiddles.count(pl.n)) {
-                std::vector<double> w(2 * (size_t)pl.n);
-                twiddles_fp64(pl.n, w.data());
-                void *d = nullptr;
-                const size_t bytes = (size_t)pl.n * compute_bytes(p->dtype);
-                if ((e = hipMalloc(&d, bytes)) != hipSuccess) {
-                    (void)hipGetLastError();
-                    return fail(CROFT_ERR_OUT_OF_MEMORY, "twiddle table: %s", hipGetErrorString(e));
-                }
-                p->twiddles[pl.n] = d;
-                p->work_bytes += bytes;
-                if (dbl) {
-                    e = hipMemcpy(d, w.data(), bytes, hipMemcpyHostToDevice);
-                } else {
-                    std::vector<float> f(w.size());
-                    for (size_t i = 0; i < w.size(); ++i) f[i] = (float)w[i];  // round to nearest even
-                    e = hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice);
-                }
-                if (e != hipSuccess) return fail_hip(e, "twiddle upload");
-            }
-            pl.tw = pl.n > 1 ? p->twiddles[pl.n] : nullptr;
-            const int rc = prepare_kernel(&pl.cfg);
-            if (rc != CROFT_SUCCESS) return rc;
+            int rc;
+            pl.tw = nullptr;
+            if (pl.n > 1 && (rc = table(pl.n, &pl.tw)) != CROFT_SUCCESS) return rc;
+            if (pl.kind == kRealX && (rc = table(2 * pl.n, &pl.tw2)) != CROFT_SUCCESS) return rc;
+            if ((rc = prepare_kernel(&pl.cfg)) != CROFT_SUCCESS) return rc;
         }
+    }
+    if (p->real && p->dir == CROFT_BACKWARD && p->passes[0].size() > 1) {
+        const Geometry &g = p->grids[0];
+        const size_t bytes = ((size_t)g.nx / 2 + 1) * g.ny * g.nz * compute_bytes(p->dtype);
+        if ((e = hipMalloc(&p->rwork, bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "real backward work buffer: %s", hipGetErrorString(e));
+        }
+        p->work_bytes += bytes;
     }
     if (is_half(p->dtype)) {
         const Geometry &g = p->grids[0];
@@ -480,7 +560,8 @@ int build_batch_tables(croft_plan *p) {
     return CROFT_SUCCESS;
 }
 
-croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int flags, int slabs) {
+croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int flags, int slabs,
+                     bool batched = false, bool real = false) {
     croft_plan *p = new (std::nothrow) croft_plan;
     if (!p) {
         fail(CROFT_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -494,8 +575,11 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
     p->offsets.assign(1, 0);
     for (const Geometry &g : grids) p->offsets.push_back(p->offsets.back() + (size_t)g.nx * g.ny * g.nz);
     p->passes.resize(grids.size());
+    p->real = real;
     for (size_t i = 0; i < grids.size(); ++i) {
-        if (build_passes(grids[i], dtype, flags, &p->passes[i]) != CROFT_SUCCESS) {
+        const int rc = real ? build_real_passes(grids[i], dtype, dir, flags, &p->passes[i])
+                            : build_passes(grids[i], dtype, flags, &p->passes[i]);
+        if (rc != CROFT_SUCCESS) {
             delete p;
             return nullptr;
         }
@@ -510,7 +594,7 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
         delete p;
         return nullptr;
     }
-    p->batched = grids.size() > 1;
+    p->batched = batched;
     if (attach_resources(p) != CROFT_SUCCESS || ((flags & CROFT_MEASURE) && measure_passes(p) != CROFT_SUCCESS) ||
         (p->batched && build_batch_tables(p) != CROFT_SUCCESS)) {
         std::string msg = g_last_error;
@@ -560,6 +644,18 @@ int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *
              hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
     const std::vector<PassLaunch> &ps = p->passes[gi];
     const bool half = is_half(p->dtype);
+    if (p->real && p->dir == CROFT_BACKWARD) {
+        // complex passes from `in` into the work buffer, the real x pass from
+        // there into `out`
+        for (size_t i = 0; i < ps.size(); ++i) {
+            const bool last = i + 1 == ps.size();
+            const void *src = i == 0 ? (const void *)in : (const void *)p->rwork;
+            void *dst = last ? (void *)out : p->rwork;
+            const int rc = run_pass(p, ps[i], src, dst, nullptr, nullptr, s, prof);
+            if (rc != CROFT_SUCCESS) return rc;
+        }
+        return CROFT_SUCCESS;
+    }
     for (size_t i = 0; i < ps.size(); ++i) {
         const void *src = i == 0 ? (const void *)in : (const void *)out;
         const int8_t *ie = nullptr;
@@ -673,12 +769,36 @@ int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
     return CROFT_SUCCESS;
 }
 
+// Bytes of the real grid and of its half spectrum (real plans).
+void real_bytes(const croft_plan *p, size_t *real_b, size_t *spec_b) {
+    const Geometry &g = p->grids[0];
+    const size_t cb = element_bytes(p->dtype);
+    *real_b = (size_t)g.nx * g.ny * g.nz * (cb / 2);
+    *spec_b = ((size_t)g.nx / 2 + 1) * g.ny * g.nz * cb;
+}
+
+// The real x pass reads (writes) the real grid and writes (reads) the half
+// spectrum; each complex pass reads and writes the half spectrum.
+double real_algorithmic_bytes(const std::vector<PassLaunch> &ps, size_t real_b, size_t spec_b) {
+    double b = 0;
+    for (const PassLaunch &pl : ps) b += pl.kind == kRealX ? (double)real_b + spec_b : 2.0 * spec_b;
+    return b;
+}
+
 int check_buffers(croft_plan *p, const void *in, const void *out) {
     if (!in || !out) return fail(CROFT_ERR_INVALID_VALUE, "NULL data pointer");
-    const size_t bytes = p->offsets.back() * element_bytes(p->dtype);
     const char *a = (const char *)in, *b = (const char *)out;
-    if (a != b && a < b + bytes && b < a + bytes)
-        return fail(CROFT_ERR_INVALID_VALUE, "in and out overlap without being equal");
+    if (p->real) {
+        size_t rb, sb;
+        real_bytes(p, &rb, &sb);
+        const size_t ib = p->dir == CROFT_FORWARD ? rb : sb, ob = p->dir == CROFT_FORWARD ? sb : rb;
+        if (a < b + ob && b < a + ib)
+            return fail(CROFT_ERR_INVALID_VALUE, "real transforms run out of place: in and out overlap");
+    } else {
+        const size_t bytes = p->offsets.back() * element_bytes(p->dtype);
+        if (a != b && a < b + bytes && b < a + bytes)
+            return fail(CROFT_ERR_INVALID_VALUE, "in and out overlap without being equal");
+    }
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
         return fail(CROFT_ERR_INVALID_VALUE, "the current device (%d) is not the plan's device (%d)", dev,
@@ -697,6 +817,54 @@ int execute_any(croft_plan *p, const void *in, const int8_t *in_exp, void *out, 
         rc = run_grid(p, 0, (const char *)in, (char *)out, in_exp, out_exp, s, prof);
     if (prof) p->prof.push_back(std::move(rec));
     return rc;
+}
+
+// Dry-run description shared by the complex and real forms.
+int describe_impl(int nx, int ny, int nz, int dtype, int dir, bool real, char *buf, size_t len) {
+    g_last_error.clear();
+    int rc = check_dtype_dir(dtype, dir);
+    if (rc != CROFT_SUCCESS) return rc;
+    rc = real ? check_real_dims(nx, ny, nz, dtype) : check_dims(nx, ny, nz);
+    if (rc != CROFT_SUCCESS) return rc;
+    if (!buf && len) return fail(CROFT_ERR_INVALID_VALUE, "NULL buffer");
+    const Geometry g{nx, ny, nz};
+    std::vector<PassLaunch> ps;
+    rc = real ? build_real_passes(g, dtype, dir, 0, &ps) : build_passes(g, dtype, 0, &ps);
+    if (rc != CROFT_SUCCESS) return rc;
+    if (is_half(dtype) && (rc = check_exp_maps(g, ps)) != CROFT_SUCCESS) return rc;
+    static const char *names[] = {"c64", "c128", "c16f", "c16b"};
+    static const char *kind_names[] = {"contiguous", "strided", "real"};
+    std::string s;
+    char line[512];
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t eb = element_bytes(dtype);
+    const size_t spec_b = ((size_t)nx / 2 + 1) * ny * nz * eb;
+    const double alg = real ? real_algorithmic_bytes(ps, N * (eb / 2), spec_b) : 6.0 * N * eb;
+    snprintf(line, sizeof line, "grid %dx%dx%d %s%s %s elements=%zu bytes=%zu algorithmic_bytes=%.0f\n", nx, ny,
+             nz, names[dtype], real ? " real" : "", dir == CROFT_FORWARD ? "forward" : "backward", N,
+             real ? spec_b : N * eb, alg);
+    s += line;
+    for (size_t i = 0; i < ps.size(); ++i) {
+        const PassLaunch &pl = ps[i];
+        std::string rad;
+        for (int k = 0; k < pl.cfg.nstages; ++k) rad += (k ? "x" : "") + std::to_string(pl.cfg.radix[k]);
+        if (rad.empty()) rad = "copy";
+        const long long blocks = pass_tiles(pl);
+        snprintf(line, sizeof line,
+                 "pass %zu axis=%c n=%d kind=%s kernel=%s radices=%s stride=%lld lines=%lld T=%d L=%d block=%d "
+                 "blocks=%lld lds=%zu candidate=%d waves=%d\n",
+                 i, "xyz"[pl.axis], pl.n, kind_names[pl.kind],
+                 pl.cfg.generic ? "generic" : "static", rad.c_str(), pl.es,
+                 pl.kind != kStrided ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
+                 pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves);
+        s += line;
+    }
+    if (len) {
+        const size_t n = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = '\0';
+    }
+    return CROFT_SUCCESS;
 }
 
 }  // namespace
@@ -733,7 +901,7 @@ int croft_plan_destroy(croft_plan_t plan) {
 
 int croft_execute(croft_plan_t p, const void *in, void *out, hipStream_t stream) {
     if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
-    if (p->grids.size() != 1) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
+    if (p->batched) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
     if (is_half(p->dtype))
         return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "half-storage plan: use croft_execute_scaled");
     const int rc = check_buffers(p, in, out);
@@ -744,7 +912,7 @@ int croft_execute(croft_plan_t p, const void *in, void *out, hipStream_t stream)
 int croft_execute_scaled(croft_plan_t p, const void *in, const int8_t *in_exp, void *out, int8_t *out_exp,
                          hipStream_t stream) {
     if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
-    if (p->grids.size() != 1) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
+    if (p->batched) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
     if (!is_half(p->dtype))
         return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "croft_execute_scaled needs a CROFT_C16F/CROFT_C16B plan");
     if (!out_exp) return fail(CROFT_ERR_INVALID_VALUE, "NULL out_exp");
@@ -789,7 +957,18 @@ croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, in
         fail(CROFT_ERR_UNSUPPORTED_SIZE, "batch of %lld elements exceeds 2^31 - 1", total);
         return nullptr;
     }
-    return new_plan(grids, dtype, dir, flags, 1);
+    return new_plan(grids, dtype, dir, flags, 1, true);
+}
+
+croft_plan_t croft_plan_create_real(int nx, int ny, int nz, int dtype, int dir, int flags) {
+    g_last_error.clear();
+    if (check_dtype_dir(dtype, dir) != CROFT_SUCCESS) return nullptr;
+    if (check_real_dims(nx, ny, nz, dtype) != CROFT_SUCCESS) return nullptr;
+    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
+        fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
+        return nullptr;
+    }
+    return new_plan({Geometry{nx, ny, nz}}, dtype, dir, flags, 1, false, true);
 }
 
 int croft_plan_batched_offsets(croft_plan_t p, size_t *elem_offsets) {
@@ -800,6 +979,7 @@ int croft_plan_batched_offsets(croft_plan_t p, size_t *elem_offsets) {
 
 int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t stream) {
     if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    if (!p->batched) return fail(CROFT_ERR_INVALID_VALUE, "not a batched plan: use croft_execute");
     int rc = check_buffers(p, in, out);
     if (rc != CROFT_SUCCESS) return rc;
     if (p->profiling) {
@@ -854,7 +1034,8 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
     info->nz = g.nz;
     info->dtype = p->dtype;
     info->dir = p->dir;
-    info->batched_count = p->grids.size() > 1 ? (int)p->grids.size() : 0;
+    info->batched_count = p->batched ? (int)p->grids.size() : 0;
+    info->real = p->real ? 1 : 0;
     info->slabs = p->slabs;
     const std::vector<PassLaunch> &ps = p->passes[0];
     info->npasses = (int)std::min<size_t>(ps.size(), CROFT_MAX_PASSES);
@@ -870,8 +1051,7 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
         pi.threads_per_line = pl.cfg.threads_per_line;
         pi.lines_per_block = pl.cfg.lines;
         pi.block_threads = pl.cfg.block;
-        pi.blocks = pl.kind == kContiguous ? (pl.nlines + pl.cfg.lines - 1) / pl.cfg.lines
-                                           : ((pl.es + pl.cfg.lines - 1) / pl.cfg.lines) * pl.nw;
+        pi.blocks = pass_tiles(pl);
         pi.lds_bytes = pl.cfg.lds;
     }
     info->elements = p->offsets.back();
@@ -884,51 +1064,21 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
         if (n > 1) fl += 5.0 * n * std::log2(n);
     }
     info->flops = fl;
+    if (p->real) {
+        size_t rb, sb;
+        real_bytes(p, &rb, &sb);
+        info->algorithmic_bytes = real_algorithmic_bytes(p->passes[0], rb, sb);
+        info->flops = fl / 2;
+    }
     return CROFT_SUCCESS;
 }
 
 int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len) {
-    g_last_error.clear();
-    int rc = check_dtype_dir(dtype, dir);
-    if (rc != CROFT_SUCCESS) return rc;
-    rc = check_dims(nx, ny, nz);
-    if (rc != CROFT_SUCCESS) return rc;
-    if (!buf && len) return fail(CROFT_ERR_INVALID_VALUE, "NULL buffer");
-    const Geometry g{nx, ny, nz};
-    std::vector<PassLaunch> ps;
-    rc = build_passes(g, dtype, 0, &ps);
-    if (rc != CROFT_SUCCESS) return rc;
-    if (is_half(dtype) && (rc = check_exp_maps(g, ps)) != CROFT_SUCCESS) return rc;
-    static const char *names[] = {"c64", "c128", "c16f", "c16b"};
-    std::string s;
-    char line[512];
-    const size_t N = (size_t)nx * ny * nz;
-    snprintf(line, sizeof line, "grid %dx%dx%d %s %s elements=%zu bytes=%zu algorithmic_bytes=%.0f\n", nx, ny, nz,
-             names[dtype], dir == CROFT_FORWARD ? "forward" : "backward", N, N * element_bytes(dtype),
-             6.0 * N * element_bytes(dtype));
-    s += line;
-    for (size_t i = 0; i < ps.size(); ++i) {
-        const PassLaunch &pl = ps[i];
-        std::string rad;
-        for (int k = 0; k < pl.cfg.nstages; ++k) rad += (k ? "x" : "") + std::to_string(pl.cfg.radix[k]);
-        if (rad.empty()) rad = "copy";
-        const long long blocks = pl.kind == kContiguous ? (pl.nlines + pl.cfg.lines - 1) / pl.cfg.lines
-                                                        : ((pl.es + pl.cfg.lines - 1) / pl.cfg.lines) * pl.nw;
-        snprintf(line, sizeof line,
-                 "pass %zu axis=%c n=%d kind=%s kernel=%s radices=%s stride=%lld lines=%lld T=%d L=%d block=%d "
-                 "blocks=%lld lds=%zu candidate=%d waves=%d\n",
-                 i, "xyz"[pl.axis], pl.n, pl.kind == kContiguous ? "contiguous" : "strided",
-                 pl.cfg.generic ? "generic" : "static", rad.c_str(), pl.es,
-                 pl.kind == kContiguous ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
-                 pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves);
-        s += line;
-    }
-    if (len) {
-        const size_t n = std::min(len - 1, s.size());
-        std::memcpy(buf, s.data(), n);
-        buf[n] = '\0';
-    }
-    return CROFT_SUCCESS;
+    return describe_impl(nx, ny, nz, dtype, dir, false, buf, len);
+}
+
+int croft_plan_describe_real(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len) {
+    return describe_impl(nx, ny, nz, dtype, dir, true, buf, len);
 }
 
 int croft_plan_status(croft_plan_t p, int *device_status) {

@@ -313,6 +313,7 @@ struct PassArgs {
     long long ntiles;  // strided: tiles of L lines per w
     long long total;   // tiles in the launch
     ExpMap em;
+    const void *tw2;   // real x pass: w_N^k, N = 2 n (the real line length)
     int inverse;       // runtime-radix kernel only (static kernels take it as a template argument)
     // runtime-radix kernel only
     int n, T, L, S;
@@ -529,7 +530,12 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
     }
 }
 
-template <class Cfg, class St, int KIND, bool INV, int S>
+// IO bit 0: the first stage reads its inputs from LDS (natural order)
+// instead of the tile; bit 1: the last stage writes its outputs to LDS
+// (natural order) instead of global memory.
+constexpr int kFromLds = 1, kToLds = 2;
+
+template <class Cfg, class St, int KIND, bool INV, int S, int IO = 0>
 __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::R> *lds,
                                              const cx<typename St::R> *tws, unsigned *red, int t, int l,
                                              const TileCoord &c, unsigned lane, long long es,
@@ -555,7 +561,9 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
         if (!kGuard || j < NB) {
 #pragma unroll
             for (int q = 0; q < RAD; ++q) {
-                if constexpr (S == 0) {
+                if constexpr (S == 0 && (IO & kFromLds)) {
+                    v[b][q] = maybe_swap<INV>(lds[lds_index<KIND, LS, PAD>(l, j + q * NB, L)]);
+                } else if constexpr (S == 0) {
                     if constexpr (Tile<Cfg, St>::kRaw)
                         v[b][q] = maybe_swap<INV>(St::decode(tl.e[b][q], St::kHalf ? tl.ex[b][q] : 0));
                     else
@@ -576,7 +584,19 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
         if constexpr (B > 1) __builtin_amdgcn_sched_barrier(0);
     }
 
-    if constexpr (kLast) {
+    if constexpr (kLast && (IO & kToLds)) {
+        // outputs of the last stage in natural order (index j + q * NB) into LDS
+        if constexpr (S > 0 || (IO & kFromLds)) stage_sync<Cfg::kWaveSync>();
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + b * T;
+            if (!kGuard || j < NB) {
+#pragma unroll
+                for (int q = 0; q < RAD; ++q)
+                    lds[lds_index<KIND, LS, PAD>(l, j + q * NB, L)] = maybe_swap<INV>(v[b][q]);
+            }
+        }
+    } else if constexpr (kLast) {
         // outputs of the last stage: index j + q * NB (Ns * RAD == N)
         int ex = 0;
         if constexpr (St::kHalf) {
@@ -608,7 +628,7 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
             }
         }
     } else {
-        if constexpr (S > 0) stage_sync<Cfg::kWaveSync>();
+        if constexpr (S > 0 || (IO & kFromLds)) stage_sync<Cfg::kWaveSync>();
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = t + b * T;
@@ -620,7 +640,7 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
             }
         }
         stage_sync<Cfg::kWaveSync>();
-        static_stage<Cfg, St, KIND, INV, S + 1>(a, lds, tws, red, t, l, c, lane, es, tl, ex_out);
+        static_stage<Cfg, St, KIND, INV, S + 1, IO>(a, lds, tws, red, t, l, c, lane, es, tl, ex_out);
     }
 }
 
@@ -716,6 +736,84 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
         tile = nt;
         tx = ntx;
         w = nw;
+    }
+}
+
+// ------------------------------------------------------------ real transforms
+// The x pass of a real-to-complex (forward) or complex-to-real (backward)
+// transform of real lines of even length N = 2M.  A real line is read (or
+// written) as the complex line z[n] = x[2n] + i x[2n+1] of length M, whose
+// M-point FFT runs through LDS as in the complex passes.  Forward, the
+// half spectrum follows from Z = DFT_M(z) as
+//   X[k] = (A + B)/2 - i w^k (A - B)/2,  A = Z[k mod M], B = conj Z[(M-k) mod M],
+// for k = 0..M, w = exp(-2 pi i/N).  Backward, the unnormalised inverse of the
+// half spectrum X[0..M] starts from
+//   Z'[k] = (A + B) + i conj(w^k) (A - B),  A = X[k], B = conj X[M-k],  k < M,
+// whose unnormalised M-point inverse is N (x[2n] + i x[2n+1]).  The imaginary
+// parts of X[0] and X[M] are dropped (they vanish for the spectrum of a real
+// line), which makes the backward result the real inverse of the Hermitian
+// extension of any half spectrum.
+// Lines: l = y + ny z; real lines are M complex apart, spectra M + 1.
+template <class Cfg, class St, bool INV>
+__global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
+    using R = typename St::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int M = Cfg::plan.n;
+    constexpr int T = Cfg::T;
+    constexpr int L = Cfg::L;
+    constexpr int LS = Cfg::kLineStride;
+    constexpr int PAD = LS != M;
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
+    unsigned *red = nullptr;
+    const cx<R> *W2 = reinterpret_cast<const cx<R> *>(a.tw2);
+    const int tid = threadIdx.x;
+    const int l = tid / T;
+    const int t = tid % T;
+    if constexpr (Cfg::kTwN > 0) {
+        const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
+        for (int i = tid; i < Cfg::kTwN; i += Cfg::kBlock) tws[i] = W[tw_source<Cfg>(i)];
+        __syncthreads();
+    }
+    const unsigned lane = lane_offset<Cfg, St, kContiguous>(l, t, 1);
+    for (long long tile = blockIdx.x; tile < a.total; tile += gridDim.x) {
+        const TileCoord c = tile_coord<Cfg, kContiguous>(a, tile, 0, l);
+        int ex = 0;
+        if constexpr (!INV) {
+            Tile<Cfg, St> cur;
+            fetch_tile<Cfg, St, kContiguous, false>(a, c, t, lane, 1, cur);
+            static_stage<Cfg, St, kContiguous, false, 0, kToLds>(a, lds, tws, red, t, l, c, lane, 1, cur, ex);
+            stage_sync<Cfg::kWaveSync>();
+            if (c.valid) {
+                const long long ob = c.q * (M + 1);
+                for (int k = t; k <= M; k += T) {
+                    const cx<R> A = lds[lds_index<kContiguous, LS, PAD>(l, k % M, L)];
+                    const cx<R> Bc = lds[lds_index<kContiguous, LS, PAD>(l, (M - k) % M, L)];
+                    const cx<R> B = {Bc.x, -Bc.y};
+                    const cx<R> s = {(A.x + B.x) * R(0.5), (A.y + B.y) * R(0.5)};
+                    const cx<R> d = {(A.x - B.x) * R(0.5), (A.y - B.y) * R(0.5)};
+                    const cx<R> wd = cmul(W2[k], d);               // w^k (A - B)/2
+                    St::store(a.out, ob + k, cx<R>{s.x + wd.y, s.y - wd.x}, 0);  // s - i wd
+                }
+            }
+        } else {
+            if (c.valid) {
+                const cx<R> *X = reinterpret_cast<const cx<R> *>(a.in) + c.q * (M + 1);
+                for (int k = t; k < M; k += T) {
+                    cx<R> A = X[k];
+                    const cx<R> Bc = X[M - k];
+                    cx<R> B = {Bc.x, -Bc.y};
+                    if (k == 0) A.y = B.y = R(0);  // only Re X[0] and Re X[M] enter a real line
+                    const cx<R> w = W2[k];
+                    const cx<R> d = cmul(cx<R>{A.x - B.x, A.y - B.y}, cx<R>{w.x, -w.y});  // conj(w^k)(A - B)
+                    lds[lds_index<kContiguous, LS, PAD>(l, k, L)] = cx<R>{A.x + B.x - d.y, A.y + B.y + d.x};
+                }
+            }
+            stage_sync<Cfg::kWaveSync>();
+            Tile<Cfg, St> none;
+            static_stage<Cfg, St, kContiguous, true, 0, kFromLds>(a, lds, tws, red, t, l, c, lane, 1, none, ex);
+        }
+        stage_sync<Cfg::kWaveSync>();
     }
 }
 
@@ -905,6 +1003,26 @@ Entry make_entry(int cand) {
     e.cand = cand;
     e.func[0] = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND, false>);
     e.func[1] = reinterpret_cast<const void *>(&fft_static<Cfg, St, KIND, true>);
+    e.T = Cfg::T;
+    e.L = Cfg::L;
+    e.block = Cfg::kBlock;
+    e.lds = Cfg::kLds;
+    e.plan = Cfg::plan;
+    return e;
+}
+
+// The real x pass of length 2N on the contiguous configuration of length N.
+template <int N, class St, int SB, int DT>
+Entry make_real_entry() {
+    using Cfg = SCfg<N, kContiguous, SB, (int)sizeof(cx<typename St::R>), 0, 0, 0, 1>;
+    static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    Entry e;
+    e.n = N;
+    e.kind = kRealX;
+    e.dtype = DT;
+    e.cand = 0;
+    e.func[0] = reinterpret_cast<const void *>(&fft_real_x<Cfg, St, false>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_real_x<Cfg, St, true>);
     e.T = Cfg::T;
     e.L = Cfg::L;
     e.block = Cfg::kBlock;

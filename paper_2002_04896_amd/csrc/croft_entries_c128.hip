@@ -8,7 +8,7 @@
 namespace croft {
 namespace dev {
 
-#define DEF(N) make_entry<N, kContiguous, StC128, 16, kC128>(0), make_entry<N, kStrided, StC128, 16, kC128>(0)
+#define DEF(N) make_entry<N, kContiguous, StC128, 16, kC128>(0), make_entry<N, kStrided, StC128, 16, kC128>(0), make_real_entry<N, StC128, 16, kC128>()
 // contiguous: 1 padded LDS lines, 2 no prefetch;
 // strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
 // 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines)

@@ -16,7 +16,10 @@ constexpr int kMaxStages = 12;
 constexpr int kMaxLength = 4096;
 
 enum Dtype { kC64 = 0, kC128 = 1, kC16F = 2, kC16B = 3 };
-enum PassKind { kContiguous = 0, kStrided = 1 };
+// kRealX: the x pass of a real transform; contiguous geometry over the
+// half-length complex view of the real lines (n = nx / 2), spectra of
+// n + 1 elements per line.
+enum PassKind { kContiguous = 0, kStrided = 1, kRealX = 2 };
 
 inline size_t element_bytes(int dtype) {
     return dtype == kC128 ? 16 : (dtype == kC64 ? 8 : 4);
@@ -65,6 +68,7 @@ struct PassLaunch {
     long long nw = 1;      // strided: number of w
     KernelConfig cfg;
     const void *tw = nullptr;  // device twiddle table of length n (dtype's compute type)
+    const void *tw2 = nullptr; // kRealX: device twiddle table of length 2 n
     ExpMap em;
 };
 

@@ -178,7 +178,7 @@ int kernel_candidates(int n, int kind, int dtype) {
 
 bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, KernelConfig *cfg) {
     if (n < 1 || n > kMaxLength) return false;
-    if (!force_generic) {
+    if (!force_generic || kind == kRealX) {
         const Entry *pick = nullptr;
         for (const Entry &e : table()) {
             if (e.n == n && e.kind == kind && e.dtype == dtype) {
@@ -200,6 +200,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
             return true;
         }
     }
+    if (kind == kRealX) return false;  // real x passes run compiled configurations only
     const RPlan p = make_rplan(n);
     if (p.S < 0) return false;
     const int cb = dtype == kC128 ? 16 : 8;                      // compute bytes
@@ -237,7 +238,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
 
 long long pass_tiles(const PassLaunch &pl) {
     const int L = pl.cfg.lines;
-    if (pl.kind == kContiguous) return (pl.nlines + L - 1) / L;
+    if (pl.kind != kStrided) return (pl.nlines + L - 1) / L;
     return ((pl.es + L - 1) / L) * pl.nw;
 }
 
@@ -248,6 +249,7 @@ hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *ou
     a.in = in;
     a.out = out;
     a.tw = pl.tw;
+    a.tw2 = pl.tw2;
     a.in_exp = in_exp;
     a.out_exp = out_exp;
     a.es = pl.es;
@@ -259,8 +261,8 @@ hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *ou
     a.L = pl.cfg.lines;
     a.S = pl.cfg.nstages;
     for (int s = 0; s < kMaxStages; ++s) a.radix[s] = pl.cfg.radix[s];
-    a.nlines = pl.kind == kContiguous ? pl.nlines : pl.es;
-    a.ntiles = pl.kind == kContiguous ? 1 : (pl.es + a.L - 1) / a.L;
+    a.nlines = pl.kind != kStrided ? pl.nlines : pl.es;
+    a.ntiles = pl.kind != kStrided ? 1 : (pl.es + a.L - 1) / a.L;
     a.total = pass_tiles(pl);
     if (a.total <= 0) return hipSuccess;
     long long blocks = a.total;

@@ -167,3 +167,49 @@ def test_every_candidate_fits_the_device(tmp_path, monkeypatch):
                                                    n, n if kind else 2, 4, dt)
                     for p in passes:
                         assert int(p["block"]) <= 1024 and int(p["lds"]) <= 160 * 1024
+
+
+# ------------------------------------------------------------ real plans
+def test_describe_real_512_cube_forward_and_backward():
+    head, passes = parse_describe(croft.croft_plan_describe_real(512, 512, 512))
+    spec = 257 * 512 * 512
+    assert "real forward" in head and f"bytes={spec * 8}" in head
+    # x pass: real grid (4 B per value) + half spectrum; y, z: twice the half spectrum
+    assert f"algorithmic_bytes={512 ** 3 * 4 + spec * 8 + 4 * spec * 8}" in head
+    assert [p["axis"] for p in passes] == ["x", "y", "z"]
+    assert [p["kind"] for p in passes] == ["real", "strided", "strided"]
+    assert [p["n"] for p in passes] == ["256", "512", "512"]
+    assert [p["stride"] for p in passes] == ["1", "257", str(257 * 512)]
+    assert passes[0]["lines"] == str(512 * 512)
+    assert passes[0]["kernel"] == "static"
+    _, back = parse_describe(croft.croft_plan_describe_real(512, 512, 512, croft.CROFT_C64, croft.CROFT_BACKWARD))
+    assert [p["axis"] for p in back] == ["z", "y", "x"]
+    assert [p["kind"] for p in back] == ["strided", "strided", "real"]
+
+
+@pytest.mark.parametrize("dims,skipped", [((64, 1, 8), "y"), ((64, 8, 1), "z"), ((16, 1, 1), "yz")])
+def test_describe_real_skips_unit_axes(dims, skipped):
+    _, passes = parse_describe(croft.croft_plan_describe_real(*dims))
+    axes = [p["axis"] for p in passes]
+    assert axes[0] == "x" and not any(a in axes for a in skipped)
+
+
+@pytest.mark.parametrize("nx", [4, 8, 96, 120, 144, 160, 192, 200, 768, 1024, 8192])
+@pytest.mark.parametrize("dt", [croft.CROFT_C64, croft.CROFT_C128])
+def test_describe_real_supported_lengths_fit_the_device(nx, dt):
+    _, passes = parse_describe(croft.croft_plan_describe_real(nx, 6, 5, dt))
+    assert passes[0]["kind"] == "real" and int(passes[0]["n"]) == nx // 2
+    for p in passes:
+        assert int(p["block"]) <= 1024 and int(p["lds"]) <= 160 * 1024
+
+
+@pytest.mark.parametrize("dims,dt,msg", [
+    ((7, 4, 4), croft.CROFT_C64, "even nx"), ((2, 4, 4), croft.CROFT_C64, "even nx"),
+    ((8194, 4, 4), croft.CROFT_C64, "even nx"), ((162, 4, 4), croft.CROFT_C64, "no real x kernel"),
+    ((16, 7, 4), croft.CROFT_C64, "unsupported"), ((16, 4, 4), croft.CROFT_C16F, "CROFT_C64 or CROFT_C128"),
+])
+def test_real_plans_reject_bad_arguments(dims, dt, msg):
+    with pytest.raises(ValueError, match=msg):
+        croft.croft_plan_describe_real(*dims, dt)
+    with pytest.raises(ValueError, match=msg):
+        croft.croft_plan_create_real(*dims, dt)

@@ -237,3 +237,74 @@ def test_rel_l2_values():
     assert oracle.rel_l2([3 + 4j], [0]) == 5.0
     assert oracle.rel_l2([1 + 1j, 1], [1, 1]) == pytest.approx(1 / np.sqrt(2))
     assert oracle.rel_l2([2, 0], [2, 0]) == 0.0
+
+
+# --------------------------------------------------------- real transforms
+REAL_SHAPES = [(1, 1, 4), (3, 5, 8), (4, 6, 12), (2, 3, 16), (5, 4, 10)]
+
+
+@pytest.mark.parametrize("nzyx", REAL_SHAPES, ids=str)
+def test_rdft3d_matches_numpy_rfftn(nzyx):
+    x = RNG.standard_normal(nzyx)
+    assert oracle.rel_l2(oracle.rdft3d(x), np.fft.rfftn(x, axes=(0, 1, 2))) <= 1e-13
+
+
+@pytest.mark.parametrize("nzyx", REAL_SHAPES, ids=str)
+def test_irdft3d_matches_numpy_irfftn_on_any_half_spectrum(nzyx):
+    # a half spectrum that is NOT the transform of a real grid: numpy's
+    # irfftn also drops the imaginary parts of the kx = 0 and kx = nx/2 terms
+    nz, ny, nx = nzyx
+    h = RNG.standard_normal((nz, ny, nx // 2 + 1)) + 1j * RNG.standard_normal((nz, ny, nx // 2 + 1))
+    ref = np.fft.irfftn(h, s=nzyx, axes=(0, 1, 2)) * (nx * ny * nz)
+    assert oracle.rel_l2(oracle.irdft3d(h, nx), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("nzyx", REAL_SHAPES, ids=str)
+def test_real_round_trip_is_n_identity(nzyx):
+    x = RNG.standard_normal(nzyx)
+    back = oracle.irdft3d(oracle.rdft3d(x), nzyx[2])
+    assert oracle.rel_l2(back / x.size, x) <= 1e-13
+
+
+def test_c2r_x_closed_forms():
+    nx = 12
+    n = np.arange(nx)
+    g = np.zeros(nx // 2 + 1, complex)
+    g[0] = 3 + 7j                      # imaginary part of the DC term drops out
+    np.testing.assert_allclose(oracle.c2r_x(g, nx), np.full(nx, 3.0), atol=1e-14)
+    g[:] = 0
+    g[nx // 2] = -2 + 5j               # Nyquist term: alternating, imaginary part dropped
+    np.testing.assert_allclose(oracle.c2r_x(g, nx), -2.0 * (-1.0) ** n, atol=1e-14)
+    g[:] = 0
+    c = 1.5 * np.exp(0.4j)
+    g[2] = c                           # 2 |c| cos(2 pi 2 n / nx + arg c)
+    np.testing.assert_allclose(oracle.c2r_x(g, nx), 3.0 * np.cos(2 * np.pi * 2 * n / nx + 0.4), atol=1e-13)
+
+
+def test_rdft3d_of_cosine_gives_two_bins_in_the_half():
+    nz, ny, nx = 3, 4, 16
+    x = np.zeros((nz, ny, nx))
+    x[:, :, :] = np.cos(2 * np.pi * 3 * np.arange(nx) / nx)
+    r = oracle.rdft3d(x)
+    ref = np.zeros((nz, ny, nx // 2 + 1), complex)
+    ref[0, 0, 3] = nx * ny * nz / 2
+    np.testing.assert_allclose(r, ref, atol=1e-11)
+
+
+def test_real_exact_lines_match_full_transforms():
+    nz, ny, nx = 6, 5, 20
+    x = RNG.standard_normal((nz, ny, nx))
+    r = oracle.rdft3d(x)
+    kyz = [(0, 0), (4, 5), (2, 3)]
+    assert oracle.rel_l2(oracle.rdft3d_lines(x, kyz), np.stack([r[kz, ky] for ky, kz in kyz])) <= 1e-13
+    h = RNG.standard_normal(r.shape) + 1j * RNG.standard_normal(r.shape)
+    b = oracle.irdft3d(h, nx)
+    assert oracle.rel_l2(oracle.irdft3d_lines(h, nx, kyz), np.stack([b[z, y] for y, z in kyz])) <= 1e-13
+
+
+def test_yz_sums_then_x_dft_is_the_exact_line():
+    nz, ny, nx = 4, 3, 6
+    x = rand_grid(nz, ny, nx)
+    red = oracle.yz_sums(x, [(2, 1)], -1)
+    full = oracle.dft3d_brute(x, -1)
+    assert oracle.rel_l2(np.fft.fft(red[0]), full[1, 2]) <= 1e-13
