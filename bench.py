@@ -167,6 +167,55 @@ def measure_real(torch, np, croft, pme, steps):
     return out
 
 
+def measure_conv(torch, np, croft, synth, pme, steps):
+    """The fused convolution plan (forward real transform, product with the
+    PME influence function, backward real transform, energy) on the PME grid,
+    timed next to the same steps run as separate plans, with the bitwise
+    comparison of the two."""
+    n = pme.shape[0]
+    d_x = torch.from_numpy(np.ascontiguousarray(pme.real)).cuda()
+    d_g = torch.from_numpy(synth.pme_influence(n, n, n).astype(np.float32)).cuda()
+    out = torch.empty_like(d_x)
+    d_e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan = croft.croft_plan_create_convolution(n, n, n, croft.CROFT_C64, 0)
+    info = croft.croft_plan_info(plan)
+    ms, pm, _ = time_plan(torch, croft, plan,
+                          lambda: croft.croft_execute_convolution(plan, d_x, d_g, out, d_e), steps, 3,
+                          info["npasses"])
+    croft.croft_plan_destroy(plan)
+    # unfused: real forward plan, elementwise product (torch), real backward plan
+    h = torch.empty((n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    ref = torch.empty_like(d_x)
+    f = croft.croft_plan_create_real(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD, 0)
+    b = croft.croft_plan_create_real(n, n, n, croft.CROFT_C64, croft.CROFT_BACKWARD, 0)
+    hr = torch.view_as_real(h)
+    g3 = d_g[..., None]
+
+    def unfused():
+        croft.croft_execute(f, d_x, h)
+        hr.mul_(g3)
+        croft.croft_execute(b, h, ref)
+    for _ in range(3):
+        unfused()
+    torch.cuda.synchronize()
+    a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a_.record()
+    for _ in range(steps):
+        unfused()
+    b_.record()
+    torch.cuda.synchronize()
+    ms_unfused = a_.elapsed_time(b_) / steps
+    croft.croft_plan_destroy(f)
+    croft.croft_plan_destroy(b)
+    res = {"ms": ms, "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
+           "algorithmic_bytes": info["algorithmic_bytes"], "pass_ms": pm, "energy": float(d_e.item()),
+           "unfused_ms": ms_unfused, "speedup_vs_unfused": ms_unfused / ms,
+           "bitwise_equal_to_unfused": bool(torch.equal(out, ref))}
+    del d_x, d_g, out, h, ref
+    torch.cuda.empty_cache()
+    return res
+
+
 def measure_forms(torch, np, croft, synth, steps):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
@@ -319,6 +368,7 @@ def main():
         del d_in, d_out
         torch.cuda.empty_cache()
         line["forms"] = measure_real(torch, np, croft, x, max(10, args.steps // 2))
+        line["forms"]["convolution"] = measure_conv(torch, np, croft, synth, x, max(10, args.steps // 2))
         line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2)))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, n)

@@ -179,6 +179,41 @@ int croft_execute_batched(croft_plan_t plan, const void *in, void *out, hipStrea
  * (counted in croft_plan_info.work_bytes). */
 croft_plan_t croft_plan_create_real(int nx, int ny, int nz, int dtype, int dir, int flags);
 
+/* Convolution plans: the reciprocal-space step of particle-mesh Ewald
+ * (Section 1: a forward FFT of the charge grid, a product in reciprocal
+ * space, a reverse FFT back to the grid), on a real grid, in one call:
+ *   Q   = the forward real transform of `in` (Eq. 1, half spectrum),
+ *   out = the backward real transform (as croft_plan_create_real, without
+ *         1/N) of G * Q, G the real multiplier `mul` given on the half
+ *         spectrum,
+ *   *energy = sum over the full spectrum of G(k) |Q(k)|^2, G extended to
+ *         kx > nx/2 by G(-k) = G(k) (so the kx = 1..nx/2-1 terms count twice).
+ * Passes: the forward x (real) and y passes, then ONE pass along z that
+ * transforms forward, multiplies by G and transforms back while each tile
+ * stays in LDS, then the backward y and x passes: five sweeps instead of the
+ * six of two separate transforms, and G is read once.  With nz = 1 the fused
+ * pass runs along y.
+ * dtype CROFT_C64 (float reals and multiplier, FP32 compute) or CROFT_C128
+ * (double, FP64).  Sizes as for croft_plan_create_real, plus ny*nz > 1, and
+ * the fused axis length must be a compiled length (powers of two 2..4096,
+ * 48, 60, 72, 80, 96, 100, 384).  flags: CROFT_MEASURE, CROFT_FORCE_GENERIC
+ * (y pass only), CROFT_NO_WISDOM.  The plan owns a half-spectrum work buffer
+ * and the per-block energy partials.  Returns NULL on failure. */
+croft_plan_t croft_plan_create_convolution(int nx, int ny, int nz, int dtype, int flags);
+
+/* Run a convolution plan (asynchronous on `stream`).
+ *   in:     nx*ny*nz reals (x + nx*(y + ny*z)); left unchanged unless in == out
+ *   mul:    (nx/2+1)*ny*nz reals, element (kx, ky, kz) at kx + (nx/2+1)*(ky + ny*kz)
+ *   out:    nx*ny*nz reals; may equal `in`, must not otherwise overlap it or `mul`
+ *   energy: one double in device memory, or NULL to skip the sum; computed
+ *           in FP64 from per-block partials in a fixed order (the same
+ *           inputs give the same bits). */
+int croft_execute_convolution(croft_plan_t plan, const void *in, const void *mul, void *out, double *energy,
+                              hipStream_t stream);
+
+/* Dry run of croft_plan_create_convolution (no GPU). */
+int croft_plan_describe_convolution(int nx, int ny, int nz, int dtype, char *buf, size_t len);
+
 /* Waits for the device and reports whether a persistent batched launch of
  * this plan ever had to give up waiting for a previous pass (device_status
  * 1; the results of that execute are then invalid) -- 0 otherwise and for
@@ -192,7 +227,8 @@ int croft_plan_status(croft_plan_t plan, int *device_status);
 struct croft_pass_info {
     int axis;            /* 0 = x, 1 = y, 2 = z */
     int n;               /* transform length */
-    int kind;            /* 0: contiguous lines, 1: strided lines, 2: real x pass (n = nx/2) */
+    int kind;            /* 0: contiguous lines, 1: strided lines, 2: real x pass (n = nx/2),
+                            3: fused forward / multiply / inverse pass (strided lines) */
     int generic;         /* 1 if the runtime-radix kernel runs this pass */
     int nstages;
     int radices[CROFT_MAX_STAGES];
@@ -215,7 +251,8 @@ struct croft_plan_info {
                                  plans: real grid + half spectrum for the x pass, twice the
                                  half spectrum for each of the others */
     double flops;             /* sum over grids of 5 N log2 N (real plans: 2.5 N log2 N) */
-    int real;                 /* 1 for a plan of croft_plan_create_real */
+    int real;                 /* 1 for a plan of croft_plan_create_real or _convolution */
+    int convolution;          /* 1 for a plan of croft_plan_create_convolution */
 };
 int croft_plan_info(croft_plan_t plan, struct croft_plan_info *info);
 

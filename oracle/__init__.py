@@ -21,6 +21,10 @@ What it computes (the paper, Section 2.1):
   grid: the unnormalised backward sum over z and y, then the real inverse
   of the Hermitian extension along x (``c2r_x``); ``irdft3d_lines`` gives
   exact real output lines of large grids (``yz_sums`` + ``c2r_x``).
+* ``convolve_real``      -- the reciprocal-space step of PME (Section 1): the
+  forward real transform, a product with a real multiplier on the half
+  spectrum, the backward real transform, and the sum of G |Q|^2 over the full
+  spectrum.
 * ``decode_half``        -- the exact value of FP16/BF16 storage with per-line
   power-of-two exponents (value = stored * 2**e).
 * ``rel_l2``             -- the error metric ||a - ref||_2 / ||ref||_2.
@@ -269,6 +273,35 @@ def irdft3d_lines(h, nx: int, yz) -> np.ndarray:
     """Real output lines x(0..nx-1, y, z) of ``irdft3d`` for each (y, z) in
     ``yz``: (len(yz), nx)."""
     return c2r_x(yz_sums(h, yz, BACKWARD), nx)
+
+
+def half_weights(nx: int) -> np.ndarray:
+    """How many full-spectrum bins each kx = 0..nx/2 of a half spectrum
+    stands for: 1 for kx = 0 and kx = nx/2, 2 for the rest (their mirrors
+    nx - kx hold the conjugate values)."""
+    w = np.full(nx // 2 + 1, 2.0)
+    w[0] = 1.0
+    w[nx // 2] = 1.0
+    return w
+
+
+def convolve_real(x, g):
+    """PME's reciprocal-space step on a real (nz, ny, nx) grid with a real
+    multiplier g on the half spectrum (nz, ny, nx//2 + 1):
+        Q = rdft3d(x)                      (Eq. 1, kx <= nx/2)
+        out = irdft3d(g * Q, nx)           (backward, no 1/N)
+        energy = sum over the full spectrum of G |Q|^2, G(-k) = G(k),
+               = sum over the half of half_weights(nx) * g * |Q|^2.
+    Returns (out, energy)."""
+    a = np.asarray(x, dtype=np.float64)
+    gg = np.asarray(g, dtype=np.float64)
+    nx = a.shape[2]
+    q = rdft3d(a)
+    if gg.shape != q.shape:
+        raise ValueError("multiplier must have the half-spectrum shape (nz, ny, nx//2 + 1)")
+    out = irdft3d(gg * q, nx)
+    energy = float(np.sum(half_weights(nx) * gg * (q.real ** 2 + q.imag ** 2)))
+    return out, energy
 
 
 def backward_eq2(y) -> np.ndarray:

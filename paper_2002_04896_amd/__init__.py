@@ -38,7 +38,8 @@ EXPORTED = (
     "croft_plan_destroy", "croft_last_error", "croft_plan_create_batched",
     "croft_plan_batched_offsets", "croft_execute_batched", "croft_plan_info",
     "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read", "croft_plan_status",
-    "croft_plan_create_real", "croft_plan_describe_real",
+    "croft_plan_create_real", "croft_plan_describe_real", "croft_plan_create_convolution",
+    "croft_execute_convolution", "croft_plan_describe_convolution",
 )
 
 
@@ -62,7 +63,7 @@ class PlanInfo(ctypes.Structure):
                 ("pass_", PassInfo * CROFT_MAX_PASSES),
                 ("elements", ctypes.c_size_t), ("element_bytes", ctypes.c_size_t),
                 ("work_bytes", ctypes.c_size_t), ("algorithmic_bytes", ctypes.c_double),
-                ("flops", ctypes.c_double), ("real", ctypes.c_int)]
+                ("flops", ctypes.c_double), ("real", ctypes.c_int), ("convolution", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pass_"}
@@ -114,6 +115,12 @@ def load():
     lib.croft_plan_create_real.restype = p
     lib.croft_plan_describe_real.argtypes = [i, i, i, i, i, ctypes.c_char_p, ctypes.c_size_t]
     lib.croft_plan_describe_real.restype = i
+    lib.croft_plan_create_convolution.argtypes = [i, i, i, i, i]
+    lib.croft_plan_create_convolution.restype = p
+    lib.croft_execute_convolution.argtypes = [p, vp, vp, vp, vp, vp]
+    lib.croft_execute_convolution.restype = i
+    lib.croft_plan_describe_convolution.argtypes = [i, i, i, i, ctypes.c_char_p, ctypes.c_size_t]
+    lib.croft_plan_describe_convolution.restype = i
     lib.croft_plan_status.argtypes = [p, ctypes.POINTER(ctypes.c_int)]
     lib.croft_plan_status.restype = i
     lib.croft_plan_profile.argtypes = [p, i]
@@ -220,6 +227,22 @@ def croft_plan_create_real(nx, ny, nz, dtype=CROFT_C64, dir=CROFT_FORWARD, flags
 def croft_plan_describe_real(nx, ny, nz, dtype=CROFT_C64, dir=CROFT_FORWARD) -> str:
     buf = ctypes.create_string_buffer(8192)
     _check(load().croft_plan_describe_real(nx, ny, nz, dtype, dir, buf, len(buf)))
+    return buf.value.decode()
+
+
+def croft_plan_create_convolution(nx, ny, nz, dtype=CROFT_C64, flags=0):
+    return _created(load().croft_plan_create_convolution(nx, ny, nz, dtype, flags))
+
+
+def croft_execute_convolution(plan, inp, mul, out, energy=None, stream=None) -> None:
+    """energy: None, or a one-element float64 device tensor (or address)."""
+    _check(load().croft_execute_convolution(plan, _ptr(inp), _ptr(mul), _ptr(out), _ptr(energy),
+                                            _stream(stream, inp, out)))
+
+
+def croft_plan_describe_convolution(nx, ny, nz, dtype=CROFT_C64) -> str:
+    buf = ctypes.create_string_buffer(8192)
+    _check(load().croft_plan_describe_convolution(nx, ny, nz, dtype, buf, len(buf)))
     return buf.value.decode()
 
 

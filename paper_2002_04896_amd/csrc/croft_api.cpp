@@ -54,6 +54,9 @@ struct croft_plan {
     // direction runs its complex passes in `rwork` (the input is kept)
     bool real = false;
     void *rwork = nullptr;
+    // convolution plans (real, with the fused multiply pass): energy partials
+    bool conv = false;
+    double *partial = nullptr;
     // slab schedule
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
@@ -108,6 +111,15 @@ int check_dtype_dir(int dtype, int dir) {
     return CROFT_SUCCESS;
 }
 
+// Static kernels address a thread's first element as a uniform 64-bit tile
+// base plus a 32-bit per-thread byte offset; true when that offset fits.
+bool lane_offset_fits(const PassLaunch &p, int dtype) {
+    if (p.cfg.generic) return true;
+    const long long L = p.cfg.lines, T = p.cfg.threads_per_line;
+    const long long e = strided_kind(p.kind) ? (L - 1) + (T - 1) * p.es : (L - 1) * p.n + (T - 1);
+    return (e + 1) * (long long)element_bytes(dtype) <= 0xffffffffLL;
+}
+
 // The pass list of one grid, without device resources (twiddle pointers are
 // filled in later).  Half storage always runs all three axes, so that every
 // pass re-scales its lines and the output exponents are per z-line.
@@ -134,6 +146,8 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
         int cand = 0, waves = 1;
         wisdom_lookup(n, p.kind, dtype, &cand, &waves);
         if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
+            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+        if (!lane_offset_fits(p, dtype) && !select_kernel(n, p.kind, dtype, true, 0, &p.cfg))
             return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
         p.cfg.grid_waves = waves;
         if (half) {
@@ -205,6 +219,8 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
         wisdom_lookup(n, kStrided, dtype, &cand, &waves);
         if (!select_kernel(n, kStrided, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
             return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+        if (!lane_offset_fits(p, dtype) && !select_kernel(n, kStrided, dtype, true, 0, &p.cfg))
+            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
         p.cfg.grid_waves = waves;
         yz.push_back(p);
     }
@@ -214,6 +230,41 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
     } else {
         out->insert(out->end(), yz.rbegin(), yz.rend());
         out->push_back(xp);
+    }
+    return CROFT_SUCCESS;
+}
+
+// The pass list of a convolution plan: the forward real passes up to the
+// last axis of length > 1 (z, else y), that axis as the fused forward /
+// multiply / inverse pass, then the backward passes in reverse order.
+int build_conv_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch> *out) {
+    std::vector<PassLaunch> fwd;
+    int rc = build_real_passes(g, dtype, CROFT_FORWARD, flags, &fwd);
+    if (rc != CROFT_SUCCESS) return rc;
+    if (fwd.size() < 2)
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "convolution plans need ny > 1 or nz > 1");
+    PassLaunch c = fwd.back();  // the last complex pass becomes the fused one
+    fwd.pop_back();
+    c.kind = kConvZ;
+    c.hx = (long long)g.nx / 2 + 1;
+    int cand = 0, waves = 1;
+    wisdom_lookup(c.n, kConvZ, dtype, &cand, &waves);
+    if (!select_kernel(c.n, kConvZ, dtype, false, cand, &c.cfg))
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no fused multiply kernel for length %d", c.n);
+    if (!lane_offset_fits(c, dtype))
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "grid too large for the fused multiply kernel");
+    c.cfg.grid_waves = waves;
+    out->clear();
+    for (PassLaunch pl : fwd) {
+        pl.dir = CROFT_FORWARD;
+        out->push_back(pl);
+    }
+    c.dir = CROFT_FORWARD;
+    out->push_back(c);
+    for (auto it = fwd.rbegin(); it != fwd.rend(); ++it) {
+        PassLaunch pl = *it;
+        pl.dir = CROFT_BACKWARD;
+        out->push_back(pl);
     }
     return CROFT_SUCCESS;
 }
@@ -270,6 +321,7 @@ void destroy_plan(croft_plan *p) {
     if (p->e1) (void)hipFree(p->e1);
     if (p->e2) (void)hipFree(p->e2);
     if (p->rwork) (void)hipFree(p->rwork);
+    if (p->partial) (void)hipFree(p->partial);
     for (int i = 0; i < 2; ++i) {
         if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
         if (p->join[i]) (void)hipEventDestroy(p->join[i]);
@@ -356,7 +408,17 @@ int attach_resources(croft_plan *p) {
             if ((rc = prepare_kernel(&pl.cfg)) != CROFT_SUCCESS) return rc;
         }
     }
-    if (p->real && p->dir == CROFT_BACKWARD && p->passes[0].size() > 1) {
+    if (p->conv) {
+        long long tiles = 0;
+        for (const PassLaunch &pl : p->passes[0])
+            if (pl.kind == kConvZ) tiles = pass_tiles(pl);  // most blocks any grid size launches
+        if ((e = hipMalloc((void **)&p->partial, sizeof(double) * (size_t)std::max(1LL, tiles))) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "energy partials: %s", hipGetErrorString(e));
+        }
+        p->work_bytes += sizeof(double) * (size_t)std::max(1LL, tiles);
+    }
+    if (p->real && (p->dir == CROFT_BACKWARD || p->conv) && p->passes[0].size() > 1) {
         const Geometry &g = p->grids[0];
         const size_t bytes = ((size_t)g.nx / 2 + 1) * g.ny * g.nz * compute_bytes(p->dtype);
         if ((e = hipMalloc(&p->rwork, bytes)) != hipSuccess) {
@@ -439,6 +501,13 @@ int measure_passes(croft_plan *p) {
             for (int c = 0; c < ncand && rc == CROFT_SUCCESS; ++c) {
                 KernelConfig cfg;
                 if (!select_kernel(pl.n, pl.kind, p->dtype, false, c, &cfg) || cfg.candidate != c) continue;
+                bool fits = true;
+                for (const PassLaunch *q : same) {
+                    PassLaunch t = *q;
+                    t.cfg = cfg;
+                    fits = fits && lane_offset_fits(t, p->dtype);
+                }
+                if (!fits) continue;
                 if ((rc = prepare_kernel(&cfg)) != CROFT_SUCCESS) break;
                 for (int waves : {1, 2, 4, 0}) {
                     float total = 0.f;
@@ -447,11 +516,11 @@ int measure_passes(croft_plan *p) {
                         t.cfg = cfg;
                         t.cfg.grid_waves = waves;
                         float best_rep = 1e30f;
-                        e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0);  // warm-up
+                        e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0, a, p->partial);  // warm-up
                         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
                             float ms = 0.f;
                             e = hipEventRecord(t0, 0);
-                            if (e == hipSuccess) e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0);
+                            if (e == hipSuccess) e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0, a, p->partial);
                             if (e == hipSuccess) e = hipEventRecord(t1, 0);
                             if (e == hipSuccess) e = hipEventSynchronize(t1);
                             if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
@@ -561,7 +630,7 @@ int build_batch_tables(croft_plan *p) {
 }
 
 croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int flags, int slabs,
-                     bool batched = false, bool real = false) {
+                     bool batched = false, bool real = false, bool conv = false) {
     croft_plan *p = new (std::nothrow) croft_plan;
     if (!p) {
         fail(CROFT_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -575,10 +644,12 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
     p->offsets.assign(1, 0);
     for (const Geometry &g : grids) p->offsets.push_back(p->offsets.back() + (size_t)g.nx * g.ny * g.nz);
     p->passes.resize(grids.size());
-    p->real = real;
+    p->real = real || conv;
+    p->conv = conv;
     for (size_t i = 0; i < grids.size(); ++i) {
-        const int rc = real ? build_real_passes(grids[i], dtype, dir, flags, &p->passes[i])
-                            : build_passes(grids[i], dtype, flags, &p->passes[i]);
+        const int rc = conv   ? build_conv_passes(grids[i], dtype, flags, &p->passes[i])
+                       : real ? build_real_passes(grids[i], dtype, dir, flags, &p->passes[i])
+                              : build_passes(grids[i], dtype, flags, &p->passes[i]);
         if (rc != CROFT_SUCCESS) {
             delete p;
             return nullptr;
@@ -619,7 +690,7 @@ hipEvent_t pool_event(croft_plan *p) {
 
 // Launch one pass over elements [off, off + ...) of a grid.
 int run_pass(croft_plan *p, const PassLaunch &pl, const void *in, void *out, const int8_t *ie, int8_t *oe,
-             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof, const void *mul = nullptr) {
     hipEvent_t a = nullptr, b = nullptr;
     if (prof) {
         a = pool_event(p);
@@ -627,7 +698,8 @@ int run_pass(croft_plan *p, const PassLaunch &pl, const void *in, void *out, con
         if (!a || !b) return fail(CROFT_ERR_HIP, "profiling event creation failed");
         (void)hipEventRecord(a, s);
     }
-    const hipError_t e = launch_pass(pl, p->dtype, in, out, ie, oe, p->dir == CROFT_BACKWARD, s);
+    const int dir = pl.dir ? pl.dir : p->dir;
+    const hipError_t e = launch_pass(pl, p->dtype, in, out, ie, oe, dir == CROFT_BACKWARD, s, mul, p->partial);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
     const hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return fail_hip(e2, "kernel launch");
@@ -666,6 +738,25 @@ int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *
         }
         const int rc = run_pass(p, ps[i], src, out, ie, oe, s, prof);
         if (rc != CROFT_SUCCESS) return rc;
+    }
+    return CROFT_SUCCESS;
+}
+
+// Convolution plan: `in` -> work buffer (forward x pass), complex passes and
+// the fused pass in place there, work buffer -> `out` (backward x pass), then
+// the energy sum.
+int run_conv(croft_plan *p, const void *in, const void *mul, void *out, double *energy, hipStream_t s,
+             std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    const std::vector<PassLaunch> &ps = p->passes[0];
+    for (size_t i = 0; i < ps.size(); ++i) {
+        const void *src = i == 0 ? in : (const void *)p->rwork;
+        void *dst = i + 1 == ps.size() ? out : p->rwork;
+        const int rc = run_pass(p, ps[i], src, dst, nullptr, nullptr, s, prof, mul);
+        if (rc != CROFT_SUCCESS) return rc;
+        if (ps[i].kind == kConvZ && energy) {
+            const hipError_t e = launch_sum_partials(p->partial, (int)pass_blocks(ps[i]), energy, s);
+            if (e != hipSuccess) return fail_hip(e, "energy sum launch");
+        }
     }
     return CROFT_SUCCESS;
 }
@@ -778,10 +869,12 @@ void real_bytes(const croft_plan *p, size_t *real_b, size_t *spec_b) {
 }
 
 // The real x pass reads (writes) the real grid and writes (reads) the half
-// spectrum; each complex pass reads and writes the half spectrum.
+// spectrum; each complex pass reads and writes the half spectrum; the fused
+// multiply pass also reads the multiplier (half the bytes of the spectrum).
 double real_algorithmic_bytes(const std::vector<PassLaunch> &ps, size_t real_b, size_t spec_b) {
     double b = 0;
-    for (const PassLaunch &pl : ps) b += pl.kind == kRealX ? (double)real_b + spec_b : 2.0 * spec_b;
+    for (const PassLaunch &pl : ps)
+        b += pl.kind == kRealX ? (double)real_b + spec_b : (pl.kind == kConvZ ? 2.5 : 2.0) * spec_b;
     return b;
 }
 
@@ -820,7 +913,9 @@ int execute_any(croft_plan *p, const void *in, const int8_t *in_exp, void *out, 
 }
 
 // Dry-run description shared by the complex and real forms.
-int describe_impl(int nx, int ny, int nz, int dtype, int dir, bool real, char *buf, size_t len) {
+// mode 0: complex plan, 1: real plan, 2: convolution plan
+int describe_impl(int nx, int ny, int nz, int dtype, int dir, int mode, char *buf, size_t len) {
+    const bool real = mode != 0;
     g_last_error.clear();
     int rc = check_dtype_dir(dtype, dir);
     if (rc != CROFT_SUCCESS) return rc;
@@ -829,11 +924,13 @@ int describe_impl(int nx, int ny, int nz, int dtype, int dir, bool real, char *b
     if (!buf && len) return fail(CROFT_ERR_INVALID_VALUE, "NULL buffer");
     const Geometry g{nx, ny, nz};
     std::vector<PassLaunch> ps;
-    rc = real ? build_real_passes(g, dtype, dir, 0, &ps) : build_passes(g, dtype, 0, &ps);
+    rc = mode == 2 ? build_conv_passes(g, dtype, 0, &ps)
+         : real    ? build_real_passes(g, dtype, dir, 0, &ps)
+                   : build_passes(g, dtype, 0, &ps);
     if (rc != CROFT_SUCCESS) return rc;
     if (is_half(dtype) && (rc = check_exp_maps(g, ps)) != CROFT_SUCCESS) return rc;
     static const char *names[] = {"c64", "c128", "c16f", "c16b"};
-    static const char *kind_names[] = {"contiguous", "strided", "real"};
+    static const char *kind_names[] = {"contiguous", "strided", "real", "fused"};
     std::string s;
     char line[512];
     const size_t N = (size_t)nx * ny * nz;
@@ -841,8 +938,8 @@ int describe_impl(int nx, int ny, int nz, int dtype, int dir, bool real, char *b
     const size_t spec_b = ((size_t)nx / 2 + 1) * ny * nz * eb;
     const double alg = real ? real_algorithmic_bytes(ps, N * (eb / 2), spec_b) : 6.0 * N * eb;
     snprintf(line, sizeof line, "grid %dx%dx%d %s%s %s elements=%zu bytes=%zu algorithmic_bytes=%.0f\n", nx, ny,
-             nz, names[dtype], real ? " real" : "", dir == CROFT_FORWARD ? "forward" : "backward", N,
-             real ? spec_b : N * eb, alg);
+             nz, names[dtype], mode == 2 ? " convolution" : (real ? " real" : ""),
+             dir == CROFT_FORWARD ? "forward" : "backward", N, real ? spec_b : N * eb, alg);
     s += line;
     for (size_t i = 0; i < ps.size(); ++i) {
         const PassLaunch &pl = ps[i];
@@ -855,7 +952,7 @@ int describe_impl(int nx, int ny, int nz, int dtype, int dir, bool real, char *b
                  "blocks=%lld lds=%zu candidate=%d waves=%d\n",
                  i, "xyz"[pl.axis], pl.n, kind_names[pl.kind],
                  pl.cfg.generic ? "generic" : "static", rad.c_str(), pl.es,
-                 pl.kind != kStrided ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
+                 !strided_kind(pl.kind) ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
                  pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves);
         s += line;
     }
@@ -904,9 +1001,46 @@ int croft_execute(croft_plan_t p, const void *in, void *out, hipStream_t stream)
     if (p->batched) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
     if (is_half(p->dtype))
         return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "half-storage plan: use croft_execute_scaled");
+    if (p->conv) return fail(CROFT_ERR_INVALID_VALUE, "convolution plan: use croft_execute_convolution");
     const int rc = check_buffers(p, in, out);
     if (rc != CROFT_SUCCESS) return rc;
     return execute_any(p, in, nullptr, out, nullptr, stream);
+}
+
+croft_plan_t croft_plan_create_convolution(int nx, int ny, int nz, int dtype, int flags) {
+    g_last_error.clear();
+    if (check_dtype_dir(dtype, CROFT_FORWARD) != CROFT_SUCCESS) return nullptr;
+    if (check_real_dims(nx, ny, nz, dtype) != CROFT_SUCCESS) return nullptr;
+    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
+        fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
+        return nullptr;
+    }
+    return new_plan({Geometry{nx, ny, nz}}, dtype, CROFT_FORWARD, flags, 1, false, true, true);
+}
+
+int croft_execute_convolution(croft_plan_t p, const void *in, const void *mul, void *out, double *energy,
+                              hipStream_t stream) {
+    if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    if (!p->conv) return fail(CROFT_ERR_INVALID_VALUE, "not a convolution plan");
+    if (!in || !mul || !out) return fail(CROFT_ERR_INVALID_VALUE, "NULL data pointer");
+    size_t rb, sb;
+    real_bytes(p, &rb, &sb);
+    const size_t mb = sb / 2;  // one real per spectrum element
+    const char *a = (const char *)in, *b = (const char *)out, *m = (const char *)mul;
+    if (a != b && a < b + rb && b < a + rb)
+        return fail(CROFT_ERR_INVALID_VALUE, "in and out overlap without being equal");
+    if (m < b + rb && b < m + mb) return fail(CROFT_ERR_INVALID_VALUE, "mul overlaps out");
+    if (energy && (const char *)energy < b + rb && b < (const char *)energy + sizeof(double))
+        return fail(CROFT_ERR_INVALID_VALUE, "energy overlaps out");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(CROFT_ERR_INVALID_VALUE, "the current device (%d) is not the plan's device (%d)", dev,
+                    p->device);
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rec;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof = p->profiling ? &rec : nullptr;
+    const int rc = run_conv(p, in, mul, out, energy, stream, prof);
+    if (prof) p->prof.push_back(std::move(rec));
+    return rc;
 }
 
 int croft_execute_scaled(croft_plan_t p, const void *in, const int8_t *in_exp, void *out, int8_t *out_exp,
@@ -1036,6 +1170,7 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
     info->dir = p->dir;
     info->batched_count = p->batched ? (int)p->grids.size() : 0;
     info->real = p->real ? 1 : 0;
+    info->convolution = p->conv ? 1 : 0;
     info->slabs = p->slabs;
     const std::vector<PassLaunch> &ps = p->passes[0];
     info->npasses = (int)std::min<size_t>(ps.size(), CROFT_MAX_PASSES);
@@ -1068,17 +1203,21 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
         size_t rb, sb;
         real_bytes(p, &rb, &sb);
         info->algorithmic_bytes = real_algorithmic_bytes(p->passes[0], rb, sb);
-        info->flops = fl / 2;
+        info->flops = p->conv ? fl : fl / 2;
     }
     return CROFT_SUCCESS;
 }
 
 int croft_plan_describe(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len) {
-    return describe_impl(nx, ny, nz, dtype, dir, false, buf, len);
+    return describe_impl(nx, ny, nz, dtype, dir, 0, buf, len);
 }
 
 int croft_plan_describe_real(int nx, int ny, int nz, int dtype, int dir, char *buf, size_t len) {
-    return describe_impl(nx, ny, nz, dtype, dir, true, buf, len);
+    return describe_impl(nx, ny, nz, dtype, dir, 1, buf, len);
+}
+
+int croft_plan_describe_convolution(int nx, int ny, int nz, int dtype, char *buf, size_t len) {
+    return describe_impl(nx, ny, nz, dtype, CROFT_FORWARD, 2, buf, len);
 }
 
 int croft_plan_status(croft_plan_t p, int *device_status) {

@@ -208,11 +208,14 @@ struct StC64 {
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int) {
         reinterpret_cast<float2 *>(p)[i] = make_float2(v.x, v.y);
     }
-    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int) {
+    static __device__ __forceinline__ Raw pack(cx<R> v, int) {
         vf2 w;
         w.x = v.x;
         w.y = v.y;
-        *(__attribute__((address_space(1))) vf2 *)p = w;
+        return w;
+    }
+    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int) {
+        *(__attribute__((address_space(1))) vf2 *)p = pack(v, 0);
     }
 };
 
@@ -227,11 +230,14 @@ struct StC128 {
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int) {
         reinterpret_cast<double2 *>(p)[i] = make_double2(v.x, v.y);
     }
-    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int) {
+    static __device__ __forceinline__ Raw pack(cx<R> v, int) {
         vd2 w;
         w.x = v.x;
         w.y = v.y;
-        *(__attribute__((address_space(1))) vd2 *)p = w;
+        return w;
+    }
+    static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int) {
+        *(__attribute__((address_space(1))) vd2 *)p = pack(v, 0);
     }
 };
 
@@ -277,6 +283,7 @@ struct StHalf {
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int e) {
         reinterpret_cast<unsigned *>(p)[i] = encode(v, e);
     }
+    static __device__ __forceinline__ Raw pack(cx<R> v, int e) { return encode(v, e); }
     static __device__ __forceinline__ void store_g(__attribute__((address_space(1))) char *p, cx<R> v, int e) {
         *(__attribute__((address_space(1))) unsigned *)p = encode(v, e);
     }
@@ -314,6 +321,11 @@ struct PassArgs {
     long long total;   // tiles in the launch
     ExpMap em;
     const void *tw2;   // real x pass: w_N^k, N = 2 n (the real line length)
+    // fused multiply pass: the real multiplier (data layout), per-block
+    // energy partials, and the spectrum elements per x-line (nx/2 + 1)
+    const void *mul;
+    double *partial;
+    long long hx;
     int inverse;       // runtime-radix kernel only (static kernels take it as a template argument)
     // runtime-radix kernel only
     int n, T, L, S;
@@ -385,10 +397,12 @@ constexpr int kLdsLimit = 80 * 1024;
 //        threads and the LDS budget.
 //   PAD: contiguous lines only: one padding element per 32 in LDS.
 //   PF: prefetch the next tile's loads while transforming the current one.
+//   NT: global loads and stores carry the non-temporal (streaming) hint.
 template <int N, int KIND, int STORE_BYTES, int COMPUTE_BYTES, int EPT = 0, int LREQ = 0, int PAD = 0,
-          int PF = 1>
+          int PF = 1, int NT = 0>
 struct SCfg {
     static constexpr bool kPrefetch = PF != 0;
+    static constexpr bool kNT = NT != 0;
     static constexpr RPlan plan = make_rplan(N);
     static constexpr int S = plan.S;
     static constexpr int kEpt = EPT > 0 ? EPT : plan.rmax;
@@ -483,18 +497,24 @@ __device__ __forceinline__ gchar *uniform_gptr(const void *p, long long byte_off
     return (gchar *)(((unsigned long long)hi << 32) | lo);
 }
 
-template <class St>
+template <class St, bool NT = false>
 __device__ __forceinline__ typename St::Raw fetch_at(const void *p, long long uniform_elem, unsigned lane_bytes) {
     using Raw = typename St::Raw;
     gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(Raw));
-    return *(const __attribute__((address_space(1))) Raw *)(b + lane_bytes);
+    const __attribute__((address_space(1))) Raw *q = (const __attribute__((address_space(1))) Raw *)(b + lane_bytes);
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    return *q;
 }
 
-template <class St>
+template <class St, bool NT = false>
 __device__ __forceinline__ void store_at(void *p, long long uniform_elem, unsigned lane_bytes,
                                          cx<typename St::R> v, int ex) {
     gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(typename St::Raw));
-    St::store_g(b + lane_bytes, v, ex);
+    if constexpr (NT) {
+        __builtin_nontemporal_store(St::pack(v, ex), (__attribute__((address_space(1))) typename St::Raw *)(b + lane_bytes));
+    } else {
+        St::store_g(b + lane_bytes, v, ex);
+    }
 }
 
 template <class Cfg, class St, int KIND, bool INV>
@@ -516,7 +536,7 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
 #pragma unroll
             for (int q = 0; q < TL::R0; ++q) {
                 const long long u = c.tbase + (long long)(b * Cfg::T + q * TL::NB0) * es;
-                const typename St::Raw r = fetch_at<St>(a.in, u, lane);
+                const typename St::Raw r = fetch_at<St, Cfg::kNT>(a.in, u, lane);
                 int ex = 0;
                 if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + ea3 * (j + q * TL::NB0)] : 0;
                 if constexpr (TL::kRaw) {
@@ -622,7 +642,7 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
 #pragma unroll
                     for (int q = 0; q < RAD; ++q) {
                         const long long u = c.tbase + (long long)(b * T + q * NB) * es;
-                        store_at<St>(a.out, u, lane, maybe_swap<INV>(v[b][q]), ex);
+                        store_at<St, Cfg::kNT>(a.out, u, lane, maybe_swap<INV>(v[b][q]), ex);
                     }
                 }
             }
@@ -754,67 +774,182 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
 // line), which makes the backward result the real inverse of the Hermitian
 // extension of any half spectrum.
 // Lines: l = y + ny z; real lines are M complex apart, spectra M + 1.
+// A tile's L lines are consecutive, so its spectra form one contiguous range
+// of L (M + 1) elements: the split (forward) and the merge (backward) walk
+// that range with the whole block, giving coalesced global accesses whatever
+// M + 1 is.  LDS: the tile's lines (M per line; the kx = M terms of the
+// backward input in a side column), the stage twiddles, and w_N^k, k <= M.
+// (Lengths whose table would not fit read w_N^k from global memory.)
+template <class Cfg, class CB>
+struct RealLds {
+    static constexpr int M = Cfg::plan.n;
+    static constexpr size_t kW2 = Cfg::kLdsData + (size_t)Cfg::kTwN * CB::value;
+    static constexpr bool kW2InLds =
+        kW2 + (size_t)(M + 1 + Cfg::L) * CB::value <= (size_t)160 * 1024;
+    static constexpr size_t kNyq = kW2 + (kW2InLds ? (size_t)(M + 1) * CB::value : 0);
+    static constexpr size_t kBytes = kNyq + (size_t)Cfg::L * CB::value;
+};
+
 template <class Cfg, class St, bool INV>
 __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
     using R = typename St::R;
+    using Lay = RealLds<Cfg, std::integral_constant<int, (int)sizeof(cx<R>)>>;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int M = Cfg::plan.n;
+    constexpr int H = M + 1;
     constexpr int T = Cfg::T;
     constexpr int L = Cfg::L;
     constexpr int LS = Cfg::kLineStride;
     constexpr int PAD = LS != M;
     cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
     cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
-    unsigned *red = nullptr;
+    cx<R> *w2s = reinterpret_cast<cx<R> *>(smem + Lay::kW2);
+    cx<R> *nyq = reinterpret_cast<cx<R> *>(smem + Lay::kNyq);
     const cx<R> *W2 = reinterpret_cast<const cx<R> *>(a.tw2);
+    auto w2 = [&](int k) -> cx<R> {
+        if constexpr (Lay::kW2InLds) return w2s[k];
+        else return W2[k];
+    };
+    unsigned *red = nullptr;
     const int tid = threadIdx.x;
     const int l = tid / T;
     const int t = tid % T;
-    if constexpr (Cfg::kTwN > 0) {
+    {
         const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
         for (int i = tid; i < Cfg::kTwN; i += Cfg::kBlock) tws[i] = W[tw_source<Cfg>(i)];
+        if constexpr (Lay::kW2InLds)
+            for (int i = tid; i <= M; i += Cfg::kBlock) w2s[i] = W2[i];
         __syncthreads();
     }
+    auto at = [&](int line, int k) -> cx<R> & { return lds[lds_index<kContiguous, LS, PAD>(line, k, L)]; };
     const unsigned lane = lane_offset<Cfg, St, kContiguous>(l, t, 1);
     for (long long tile = blockIdx.x; tile < a.total; tile += gridDim.x) {
         const TileCoord c = tile_coord<Cfg, kContiguous>(a, tile, 0, l);
+        const long long q0 = tile * L;
+        const int nl = (int)(a.nlines - q0 < L ? a.nlines - q0 : L);  // lines in this tile
         int ex = 0;
         if constexpr (!INV) {
             Tile<Cfg, St> cur;
             fetch_tile<Cfg, St, kContiguous, false>(a, c, t, lane, 1, cur);
             static_stage<Cfg, St, kContiguous, false, 0, kToLds>(a, lds, tws, red, t, l, c, lane, 1, cur, ex);
-            stage_sync<Cfg::kWaveSync>();
-            if (c.valid) {
-                const long long ob = c.q * (M + 1);
-                for (int k = t; k <= M; k += T) {
-                    const cx<R> A = lds[lds_index<kContiguous, LS, PAD>(l, k % M, L)];
-                    const cx<R> Bc = lds[lds_index<kContiguous, LS, PAD>(l, (M - k) % M, L)];
-                    const cx<R> B = {Bc.x, -Bc.y};
-                    const cx<R> s = {(A.x + B.x) * R(0.5), (A.y + B.y) * R(0.5)};
-                    const cx<R> d = {(A.x - B.x) * R(0.5), (A.y - B.y) * R(0.5)};
-                    const cx<R> wd = cmul(W2[k], d);               // w^k (A - B)/2
-                    St::store(a.out, ob + k, cx<R>{s.x + wd.y, s.y - wd.x}, 0);  // s - i wd
-                }
+            __syncthreads();
+            cx<R> *out = reinterpret_cast<cx<R> *>(a.out) + q0 * H;
+            for (int i = tid; i < nl * H; i += Cfg::kBlock) {
+                const int ln = i / H, k = i - ln * H;
+                const cx<R> A = at(ln, k == M ? 0 : k);
+                const cx<R> Bc = at(ln, k == 0 ? 0 : M - k);
+                const cx<R> B = {Bc.x, -Bc.y};
+                const cx<R> s = {(A.x + B.x) * R(0.5), (A.y + B.y) * R(0.5)};
+                const cx<R> d = {(A.x - B.x) * R(0.5), (A.y - B.y) * R(0.5)};
+                const cx<R> wd = cmul(w2(k), d);                         // w^k (A - B)/2
+                St::store(out, i, cx<R>{s.x + wd.y, s.y - wd.x}, 0);     // s - i wd
             }
         } else {
-            if (c.valid) {
-                const cx<R> *X = reinterpret_cast<const cx<R> *>(a.in) + c.q * (M + 1);
-                for (int k = t; k < M; k += T) {
-                    cx<R> A = X[k];
-                    const cx<R> Bc = X[M - k];
-                    cx<R> B = {Bc.x, -Bc.y};
-                    if (k == 0) A.y = B.y = R(0);  // only Re X[0] and Re X[M] enter a real line
-                    const cx<R> w = W2[k];
-                    const cx<R> d = cmul(cx<R>{A.x - B.x, A.y - B.y}, cx<R>{w.x, -w.y});  // conj(w^k)(A - B)
-                    lds[lds_index<kContiguous, LS, PAD>(l, k, L)] = cx<R>{A.x + B.x - d.y, A.y + B.y + d.x};
+            const cx<R> *X = reinterpret_cast<const cx<R> *>(a.in) + q0 * H;
+            for (int i = tid; i < nl * H; i += Cfg::kBlock) {
+                const int ln = i / H, k = i - ln * H;
+                const cx<R> v = X[i];
+                if (k < M) at(ln, k) = v;
+                else nyq[ln] = v;
+            }
+            __syncthreads();
+            // pairs (k, M - k), 0 <= k <= M/2, merged in place; k = 0 pairs with X[M]
+            constexpr int P = M / 2 + 1;
+            for (int i = tid; i < nl * P; i += Cfg::kBlock) {
+                const int ln = i / P, k = i - ln * P;
+                const int r = M - k;
+                const cx<R> xk = at(ln, k);
+                const cx<R> xr = k == 0 ? nyq[ln] : at(ln, r);
+                // Z'[k] = (A + B) + i conj(w^k) (A - B), A = X[k], B = conj X[M-k];
+                // only the real parts of X[0] and X[M] enter
+                cx<R> A = xk, B = {xr.x, -xr.y};
+                if (k == 0) A.y = B.y = R(0);
+                const cx<R> wk = w2(k);
+                const cx<R> dk = cmul(cx<R>{A.x - B.x, A.y - B.y}, cx<R>{wk.x, -wk.y});
+                at(ln, k) = cx<R>{A.x + B.x - dk.y, A.y + B.y + dk.x};
+                if (k != 0 && r != k) {
+                    // the partner: A = X[M-k], B = conj X[k]
+                    const cx<R> A2 = xr, B2 = {xk.x, -xk.y};
+                    const cx<R> wr = w2(r);
+                    const cx<R> dr = cmul(cx<R>{A2.x - B2.x, A2.y - B2.y}, cx<R>{wr.x, -wr.y});
+                    at(ln, r) = cx<R>{A2.x + B2.x - dr.y, A2.y + B2.y + dr.x};
                 }
             }
-            stage_sync<Cfg::kWaveSync>();
+            __syncthreads();
             Tile<Cfg, St> none;
             static_stage<Cfg, St, kContiguous, true, 0, kFromLds>(a, lds, tws, red, t, l, c, lane, 1, none, ex);
         }
-        stage_sync<Cfg::kWaveSync>();
+        __syncthreads();
     }
+}
+
+// ------------------------------------------------------------ fused multiply
+// The reciprocal-space step of a PME-style convolution on the half spectrum,
+// in one pass along z (strided lines, in place): forward FFT of each z-line,
+// multiplication of every element by the real multiplier G (same layout as
+// the spectrum), inverse FFT, store.  The tile stays in LDS between the two
+// transforms.  Each block also sums w(kx) G |Q|^2 over the elements it
+// multiplied (Q the full 3D spectrum at that point; w = 1 for kx = 0 and
+// kx = nx/2, else 2, which counts the mirrored half) in FP64 and writes one
+// partial per block.
+template <class Cfg, class St>
+__global__ void __launch_bounds__(Cfg::kBlock) fft_conv_z(const PassArgs a) {
+    using R = typename St::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int N = Cfg::plan.n;
+    constexpr int L = Cfg::L;
+    constexpr int B = Cfg::kBlock;
+    static_assert(B % L == 0, "a thread keeps its line across the multiply loop");
+    cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
+    double *sum = reinterpret_cast<double *>(smem);  // reuses the tile area after the last tile
+    unsigned *red = nullptr;
+    const int tid = threadIdx.x;
+    const int l = tid % L;
+    const int t = tid / L;
+    if constexpr (Cfg::kTwN > 0) {
+        const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
+        for (int i = tid; i < Cfg::kTwN; i += B) tws[i] = W[tw_source<Cfg>(i)];
+        __syncthreads();
+    }
+    const R *G = reinterpret_cast<const R *>(a.mul);
+    const long long es = a.es;
+    const unsigned lane = lane_offset<Cfg, St, kStrided>(l, t, es);
+    double acc = 0.0;
+    for (long long tile = blockIdx.x; tile < a.total; tile += gridDim.x) {
+        const long long tx = tile % a.ntiles, w = tile / a.ntiles;
+        const TileCoord c = tile_coord<Cfg, kStrided>(a, tx, w, l);
+        int ex = 0;
+        Tile<Cfg, St> cur;
+        fetch_tile<Cfg, St, kStrided, false>(a, c, t, lane, es, cur);
+        static_stage<Cfg, St, kStrided, false, 0, kToLds>(a, lds, tws, red, t, l, c, lane, es, cur, ex);
+        __syncthreads();
+        if (c.valid) {
+            // element (line l, position e) sits at LDS index e L + l
+            const long long kx = c.q % a.hx;
+            const double wgt = (kx == 0 || kx == a.hx - 1) ? 1.0 : 2.0;
+            const R *g = G + c.tbase + l;
+            for (int e = t; e < N; e += B / L) {
+                cx<R> &v = lds[e * L + l];
+                const R gv = g[(long long)e * es];
+                const double m2 = (double)v.x * v.x + (double)v.y * v.y;
+                acc = fma(wgt * (double)gv, m2, acc);
+                v = cx<R>{v.x * gv, v.y * gv};
+            }
+        }
+        __syncthreads();
+        Tile<Cfg, St> none;
+        static_stage<Cfg, St, kStrided, true, 0, kFromLds>(a, lds, tws, red, t, l, c, lane, es, none, ex);
+        __syncthreads();
+    }
+    // block sum in a fixed order: thread i's value, then a tree over the block
+    sum[tid] = acc;
+    __syncthreads();
+    for (int h = 1; h < B; h *= 2) {
+        if ((tid & (2 * h - 1)) == 0 && tid + h < B) sum[tid] += sum[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) a.partial[blockIdx.x] = sum[0];
 }
 
 // ------------------------------------------------------------ batched form
@@ -990,9 +1125,10 @@ struct Entry {
     RPlan plan;
 };
 
-template <int N, int KIND, class St, int SB, int DT, int EPT = 0, int LREQ = 0, int PAD = 0, int PF = 1>
+template <int N, int KIND, class St, int SB, int DT, int EPT = 0, int LREQ = 0, int PAD = 0, int PF = 1,
+          int NT = 0>
 Entry make_entry(int cand) {
-    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>), EPT, LREQ, PAD, PF>;
+    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>), EPT, LREQ, PAD, PF, NT>;
     static_assert(Cfg::kBlock <= 1024, "block too large");
     static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
     static_assert(Cfg::S >= 1, "length must have a radix plan");
@@ -1015,7 +1151,8 @@ Entry make_entry(int cand) {
 template <int N, class St, int SB, int DT>
 Entry make_real_entry() {
     using Cfg = SCfg<N, kContiguous, SB, (int)sizeof(cx<typename St::R>), 0, 0, 0, 1>;
-    static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    using Lay = RealLds<Cfg, std::integral_constant<int, (int)sizeof(cx<typename St::R>)>>;
+    static_assert(Lay::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
     Entry e;
     e.n = N;
     e.kind = kRealX;
@@ -1023,6 +1160,27 @@ Entry make_real_entry() {
     e.cand = 0;
     e.func[0] = reinterpret_cast<const void *>(&fft_real_x<Cfg, St, false>);
     e.func[1] = reinterpret_cast<const void *>(&fft_real_x<Cfg, St, true>);
+    e.T = Cfg::T;
+    e.L = Cfg::L;
+    e.block = Cfg::kBlock;
+    e.lds = Lay::kBytes;
+    e.plan = Cfg::plan;
+    return e;
+}
+
+// The fused multiply pass of length N on a strided configuration (EW elements
+// per thread and LW lines per tile; 0 = the default shape).
+template <int N, class St, int SB, int DT, int EW = 0, int LW = 0>
+Entry make_conv_entry(int cand) {
+    using Cfg = SCfg<N, kStrided, SB, (int)sizeof(cx<typename St::R>), EW, LW, 0, 0>;
+    static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    static_assert((size_t)Cfg::kBlock * sizeof(double) <= Cfg::kLdsData, "block sum fits the tile area");
+    Entry e;
+    e.n = N;
+    e.kind = kConvZ;
+    e.dtype = DT;
+    e.cand = cand;
+    e.func[0] = e.func[1] = reinterpret_cast<const void *>(&fft_conv_z<Cfg, St>);
     e.T = Cfg::T;
     e.L = Cfg::L;
     e.block = Cfg::kBlock;

@@ -8,17 +8,23 @@
 namespace croft {
 namespace dev {
 
-#define DEF(N) make_entry<N, kContiguous, StC128, 16, kC128>(0), make_entry<N, kStrided, StC128, 16, kC128>(0), make_real_entry<N, StC128, 16, kC128>()
+#define DEF(N) make_entry<N, kContiguous, StC128, 16, kC128>(0), make_entry<N, kStrided, StC128, 16, kC128>(0), make_real_entry<N, StC128, 16, kC128>(), \
+               make_conv_entry<N, StC128, 16, kC128>(0)
 // contiguous: 1 padded LDS lines, 2 no prefetch;
 // strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
-// 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines)
+// 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
+// 5 wide tile with non-temporal loads and stores; contiguous 3: non-temporal;
+// fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 0, 0>(2),             \
         make_entry<N, kStrided, StC128, 16, kC128, 0, 0, 0, 0>(1),                \
         make_entry<N, kStrided, StC128, 16, kC128, EW, LW, 0, 0>(2),              \
         make_entry<N, kStrided, StC128, 16, kC128, EW, LW, 0, 1>(3),              \
-        make_entry<N, kStrided, StC128, 16, kC128, EW2, LW2, 0, 0>(4)
+        make_entry<N, kStrided, StC128, 16, kC128, EW2, LW2, 0, 0>(4), \
+        make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 0, 1, 1>(3), \
+        make_entry<N, kStrided, StC128, 16, kC128, EW, LW, 0, 0, 1>(5), \
+        make_conv_entry<N, StC128, 16, kC128, EW, LW>(1)
 
 std::vector<Entry> entries_c128() {
     return {

@@ -11,14 +11,17 @@ namespace dev {
 #define DEF(N) make_entry<N, kContiguous, StHalf<false>, 4, kC16F>(0), make_entry<N, kStrided, StHalf<false>, 4, kC16F>(0)
 // contiguous: 1 padded LDS lines, 2 no prefetch;
 // strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
-// 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines)
+// 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
+// 5 wide tile with non-temporal loads and stores; contiguous 3: non-temporal
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StHalf<false>, 4, kC16F, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StHalf<false>, 4, kC16F, 0, 0, 0, 0>(2),             \
         make_entry<N, kStrided, StHalf<false>, 4, kC16F, 0, 0, 0, 0>(1),                \
         make_entry<N, kStrided, StHalf<false>, 4, kC16F, EW, LW, 0, 0>(2),              \
         make_entry<N, kStrided, StHalf<false>, 4, kC16F, EW, LW, 0, 1>(3),              \
-        make_entry<N, kStrided, StHalf<false>, 4, kC16F, EW2, LW2, 0, 0>(4)
+        make_entry<N, kStrided, StHalf<false>, 4, kC16F, EW2, LW2, 0, 0>(4), \
+        make_entry<N, kContiguous, StHalf<false>, 4, kC16F, 0, 0, 0, 1, 1>(3), \
+        make_entry<N, kStrided, StHalf<false>, 4, kC16F, EW, LW, 0, 0, 1>(5)
 
 std::vector<Entry> entries_c16f() {
     return {

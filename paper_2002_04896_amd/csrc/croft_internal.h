@@ -19,7 +19,13 @@ enum Dtype { kC64 = 0, kC128 = 1, kC16F = 2, kC16B = 3 };
 // kRealX: the x pass of a real transform; contiguous geometry over the
 // half-length complex view of the real lines (n = nx / 2), spectra of
 // n + 1 elements per line.
-enum PassKind { kContiguous = 0, kStrided = 1, kRealX = 2 };
+// kConvZ: the fused forward FFT / multiply / inverse FFT pass of a
+// convolution plan; strided geometry on the half spectrum.
+enum PassKind { kContiguous = 0, kStrided = 1, kRealX = 2, kConvZ = 3 };
+
+// Line geometry of a pass kind: strided (lines (p, w), stride es) or
+// contiguous (lines l, stride 1).
+inline bool strided_kind(int kind) { return kind == kStrided || kind == kConvZ; }
 
 inline size_t element_bytes(int dtype) {
     return dtype == kC128 ? 16 : (dtype == kC64 ? 8 : 4);
@@ -70,6 +76,8 @@ struct PassLaunch {
     const void *tw = nullptr;  // device twiddle table of length n (dtype's compute type)
     const void *tw2 = nullptr; // kRealX: device twiddle table of length 2 n
     ExpMap em;
+    int dir = 0;               // 0: the plan's direction; else CROFT_FORWARD / CROFT_BACKWARD
+    long long hx = 0;          // kConvZ: spectrum elements per x-line
 };
 
 struct Geometry {
@@ -87,8 +95,16 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
 long long pass_tiles(const PassLaunch &pl);
 // Launch one pass.  `in`/`out` point at the first element of the lines the
 // launch covers; exponent pointers likewise (half storage only).
+// mul / partial: the multiplier and the energy partials of a kConvZ pass.
 hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *out,
-                       const int8_t *in_exp, int8_t *out_exp, int inverse, hipStream_t stream);
+                       const int8_t *in_exp, int8_t *out_exp, int inverse, hipStream_t stream,
+                       const void *mul = nullptr, double *partial = nullptr);
+
+// Blocks a pass launches (persistent grids loop over the tiles).
+long long pass_blocks(const PassLaunch &pl);
+
+// energy[0] = sum of partial[0..n) in a fixed order (one block).
+hipError_t launch_sum_partials(const double *partial, int n, double *energy, hipStream_t stream);
 
 // ---- batched form (croft_batch.hip) ----
 struct BatchConfig {

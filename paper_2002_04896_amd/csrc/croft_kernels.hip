@@ -167,6 +167,22 @@ const void *generic_func(int kind, int dtype) {
     }
 }
 
+// One block of 256 threads: thread i sums partial[i], partial[i + 256], ...
+// in order, then a fixed tree over the block.
+__global__ void __launch_bounds__(256) sum_partials(const double *partial, int n, double *energy) {
+    __shared__ double s[256];
+    const int tid = threadIdx.x;
+    double v = 0.0;
+    for (int i = tid; i < n; i += 256) v += partial[i];
+    s[tid] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h /= 2) {
+        if (tid < h) s[tid] += s[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) energy[0] = s[0];
+}
+
 }  // namespace
 
 int kernel_candidates(int n, int kind, int dtype) {
@@ -178,7 +194,7 @@ int kernel_candidates(int n, int kind, int dtype) {
 
 bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, KernelConfig *cfg) {
     if (n < 1 || n > kMaxLength) return false;
-    if (!force_generic || kind == kRealX) {
+    if (!force_generic || kind == kRealX || kind == kConvZ) {
         const Entry *pick = nullptr;
         for (const Entry &e : table()) {
             if (e.n == n && e.kind == kind && e.dtype == dtype) {
@@ -200,7 +216,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
             return true;
         }
     }
-    if (kind == kRealX) return false;  // real x passes run compiled configurations only
+    if (kind == kRealX || kind == kConvZ) return false;  // compiled configurations only
     const RPlan p = make_rplan(n);
     if (p.S < 0) return false;
     const int cb = dtype == kC128 ? 16 : 8;                      // compute bytes
@@ -238,18 +254,28 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
 
 long long pass_tiles(const PassLaunch &pl) {
     const int L = pl.cfg.lines;
-    if (pl.kind != kStrided) return (pl.nlines + L - 1) / L;
+    if (!strided_kind(pl.kind)) return (pl.nlines + L - 1) / L;
     return ((pl.es + L - 1) / L) * pl.nw;
 }
 
+long long pass_blocks(const PassLaunch &pl) {
+    long long blocks = pass_tiles(pl);
+    if (!pl.cfg.generic && pl.cfg.resident > 0 && pl.cfg.grid_waves > 0)
+        blocks = std::min<long long>(blocks, (long long)pl.cfg.resident * pl.cfg.grid_waves);
+    return blocks;
+}
+
 hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *out, const int8_t *in_exp,
-                       int8_t *out_exp, int inverse, hipStream_t stream) {
+                       int8_t *out_exp, int inverse, hipStream_t stream, const void *mul, double *partial) {
     (void)dtype;
     PassArgs a;
     a.in = in;
     a.out = out;
     a.tw = pl.tw;
     a.tw2 = pl.tw2;
+    a.mul = mul;
+    a.partial = partial;
+    a.hx = pl.hx;
     a.in_exp = in_exp;
     a.out_exp = out_exp;
     a.es = pl.es;
@@ -261,18 +287,20 @@ hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *ou
     a.L = pl.cfg.lines;
     a.S = pl.cfg.nstages;
     for (int s = 0; s < kMaxStages; ++s) a.radix[s] = pl.cfg.radix[s];
-    a.nlines = pl.kind != kStrided ? pl.nlines : pl.es;
-    a.ntiles = pl.kind != kStrided ? 1 : (pl.es + a.L - 1) / a.L;
+    a.nlines = !strided_kind(pl.kind) ? pl.nlines : pl.es;
+    a.ntiles = !strided_kind(pl.kind) ? 1 : (pl.es + a.L - 1) / a.L;
     a.total = pass_tiles(pl);
     if (a.total <= 0) return hipSuccess;
-    long long blocks = a.total;
-    if (!pl.cfg.generic && pl.cfg.resident > 0 && pl.cfg.grid_waves > 0)
-        blocks = std::min<long long>(blocks, (long long)pl.cfg.resident * pl.cfg.grid_waves);
+    const long long blocks = pass_blocks(pl);
     if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     void *args[] = {&a};
     const void *f = inverse ? pl.cfg.func_inv : pl.cfg.func;
     return hipLaunchKernel(f, dim3((unsigned)blocks), dim3(pl.cfg.block), args, pl.cfg.lds, stream);
 }
 
-}  // namespace croft
+hipError_t launch_sum_partials(const double *partial, int n, double *energy, hipStream_t stream) {
+    void *args[] = {&partial, &n, &energy};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&sum_partials), dim3(1), dim3(256), args, 0, stream);
+}
 
+}  // namespace croft

@@ -12,6 +12,9 @@ stated values, Section 6.1.2; the grids below stand in for them):
   periodic grid, one charge per cell on average (particle-mesh Ewald, the
   paper's motivating application, Section 1); real valued.  Built by the C
   helper ``pme_spread.c`` (counter-based RNG, thread-count independent).
+* ``pme_influence`` -- the smooth-PME reciprocal-space multiplier on the half
+  spectrum (Gaussian-screened Coulomb kernel times the order-4 B-spline
+  moduli, Essmann et al. 1995), the real multiplier of a convolution plan.
 * ``batch_dims`` -- the uneven shapes of a batch of grids.
 * ``quantize_half`` -- an input encoded as FP16/BF16 pairs with one
   power-of-two exponent per x-line (value = stored * 2**e).
@@ -87,6 +90,36 @@ def pme_grid(nx: int, ny: int, nz: int, seed: int):
     if rc != 0:
         raise ValueError(f"bad PME grid size {(nx, ny, nz)}")
     return grid, q.value
+
+
+def pme_influence(nx: int, ny: int, nz: int, beta: float = 0.3) -> np.ndarray:
+    """Multiplier G on the half spectrum, shape (nz, ny, nx//2 + 1), float64.
+
+    Unit grid spacing (box nx x ny x nz, volume V), Ewald parameter beta (per
+    grid spacing).  For the reciprocal vector with components m_a / n_a
+    (m_a the signed frequency of bin k_a):
+        G = exp(-pi^2 |m|^2 / beta^2) / (pi V |m|^2) * B_x B_y B_z,   G(0) = 0,
+    with the order-4 B-spline moduli B_a(k) = 1 / |sum_{j=0..2} M4(j+1)
+    exp(2 pi i k j / n_a)|^2, M4(1) = M4(3) = 1/6, M4(2) = 2/3.
+    """
+    def signed(n, count):
+        k = np.arange(count)
+        return np.where(k <= n // 2, k, k - n) / n
+
+    def bmod(n, count):
+        k = np.arange(count)
+        c = np.array([1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0])
+        ph = 2.0 * np.pi * np.outer(k, np.arange(3)) / n
+        s = (c * np.exp(1j * ph)).sum(axis=1)
+        return 1.0 / np.abs(s) ** 2
+
+    hx = nx // 2 + 1
+    mx, my, mz = signed(nx, hx), signed(ny, ny), signed(nz, nz)
+    m2 = mz[:, None, None] ** 2 + my[None, :, None] ** 2 + mx[None, None, :] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        g = np.exp(-np.pi ** 2 * m2 / beta ** 2) / (np.pi * nx * ny * nz * m2)
+    g[0, 0, 0] = 0.0
+    return g * (bmod(nz, nz)[:, None, None] * bmod(ny, ny)[None, :, None] * bmod(nx, hx)[None, None, :])
 
 
 def batch_dims(seed: int, count: int = 64, lengths=BATCH_LENGTHS) -> np.ndarray:

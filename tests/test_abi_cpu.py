@@ -213,3 +213,45 @@ def test_real_plans_reject_bad_arguments(dims, dt, msg):
         croft.croft_plan_describe_real(*dims, dt)
     with pytest.raises(ValueError, match=msg):
         croft.croft_plan_create_real(*dims, dt)
+
+
+# ------------------------------------------------------ convolution plans
+def test_describe_convolution_512_cube():
+    head, passes = parse_describe(croft.croft_plan_describe_convolution(512, 512, 512))
+    spec = 257 * 512 * 512
+    assert "convolution" in head
+    # x fwd (real + spectrum), y fwd, fused z (2 + multiplier), y bwd, x bwd
+    assert f"algorithmic_bytes={2 * (512 ** 3 * 4 + spec * 8) + 4 * spec * 8 + 2.5 * spec * 8:.0f}" in head
+    assert [p["axis"] for p in passes] == ["x", "y", "z", "y", "x"]
+    assert [p["kind"] for p in passes] == ["real", "strided", "fused", "strided", "real"]
+    assert passes[2]["stride"] == str(257 * 512) and passes[2]["kernel"] == "static"
+
+
+def test_describe_convolution_fuses_y_when_nz_is_one():
+    _, passes = parse_describe(croft.croft_plan_describe_convolution(64, 48, 1))
+    assert [p["axis"] for p in passes] == ["x", "y", "x"]
+    assert passes[1]["kind"] == "fused" and passes[1]["stride"] == "33"
+
+
+@pytest.mark.parametrize("dims,dt,msg", [
+    ((16, 1, 1), croft.CROFT_C64, "ny > 1 or nz > 1"), ((16, 4, 45), croft.CROFT_C64, "no fused"),
+    ((15, 4, 4), croft.CROFT_C64, "even nx"), ((16, 4, 4), croft.CROFT_C16B, "CROFT_C64 or CROFT_C128"),
+])
+def test_convolution_plans_reject_bad_arguments(dims, dt, msg):
+    with pytest.raises(ValueError, match=msg):
+        croft.croft_plan_describe_convolution(*dims, dt)
+    with pytest.raises(ValueError, match=msg):
+        croft.croft_plan_create_convolution(*dims, dt)
+
+
+def test_static_kernels_are_only_used_where_lane_offsets_fit_32_bits():
+    # 4096 x 4096 x 100 complex128: a z-line tile spans (T-1) * 2^24 elements
+    # of 16 B beyond 4 GiB, so the z pass must take the 64-bit runtime-radix kernel
+    _, passes = parse_describe(croft.croft_plan_describe(4096, 4096, 100, croft.CROFT_C128))
+    assert passes[2]["kernel"] == "generic"
+    for p in passes:
+        T, L, es = int(p["T"]), int(p["L"]), int(p["stride"])
+        span = (L - 1) + (T - 1) * es if p["kind"] == "strided" else (L - 1) * int(p["n"]) + T - 1
+        assert p["kernel"] == "generic" or (span + 1) * 16 <= 0xFFFFFFFF
+    _, passes = parse_describe(croft.croft_plan_describe(4096, 4096, 100, croft.CROFT_C64))
+    assert passes[2]["kernel"] == "static"

@@ -308,6 +308,29 @@ def test_batched_launch_forms_match_single_grid_plans_bitwise(dtype, direction):
     assert oracle.rel_l2(got, oracle.dft3d(seen, direction)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dims", [(64, 48, 60), (45, 27, 2)], ids=["batched-kernel", "own-launches"])
+def test_batched_plan_of_one_grid_runs_it(dims):
+    nx, ny, nz = dims
+    rng = np.random.Generator(np.random.PCG64(32))
+    x = (rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))).astype(np.complex64)
+    d_in = torch.from_numpy(x).cuda()
+    ref = torch.empty_like(d_in)
+    p = croft.croft_plan_create(nx, ny, nz, C64, FWD)
+    croft.croft_execute(p, d_in, ref)
+    croft.croft_plan_destroy(p)
+    plan = croft.croft_plan_create_batched([dims], C64, FWD)
+    try:
+        with pytest.raises(ValueError, match="batched"):
+            croft.croft_execute(plan, d_in, torch.empty_like(d_in))
+        out = torch.full_like(d_in, complex(float("nan"), 0))
+        croft.croft_execute_batched(plan, d_in, out)
+        torch.cuda.synchronize()
+        assert croft.croft_plan_info(plan)["batched_count"] == 1
+    finally:
+        croft.croft_plan_destroy(plan)
+    assert torch.equal(out.view(torch.float64), ref.view(torch.float64))
+
+
 PERSISTENT_SKIP = ("the persistent single-launch batched kernel stalled in its first device run; "
                    "the flag is disabled until the cause is established")
 

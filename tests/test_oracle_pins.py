@@ -308,3 +308,57 @@ def test_yz_sums_then_x_dft_is_the_exact_line():
     red = oracle.yz_sums(x, [(2, 1)], -1)
     full = oracle.dft3d_brute(x, -1)
     assert oracle.rel_l2(np.fft.fft(red[0]), full[1, 2]) <= 1e-13
+
+
+# ------------------------------------------------------- PME convolution step
+def _circular_convolution_brute(x, h):
+    """(x (*) h)(n) = sum_j x(j) h(n - j mod shape), by direct loops."""
+    nz, ny, nx = x.shape
+    out = np.zeros_like(x)
+    for z in range(nz):
+        for y in range(ny):
+            for xx in range(nx):
+                acc = 0.0
+                for jz in range(nz):
+                    for jy in range(ny):
+                        for jx in range(nx):
+                            acc += x[jz, jy, jx] * h[(z - jz) % nz, (y - jy) % ny, (xx - jx) % nx]
+                out[z, y, xx] = acc
+    return out
+
+
+def test_convolve_real_is_the_circular_convolution_theorem():
+    # a real, even kernel h has a real spectrum; the step must give N (x (*) h)
+    nz, ny, nx = 3, 4, 6
+    x = RNG.standard_normal((nz, ny, nx))
+    h = RNG.standard_normal((nz, ny, nx))
+    h = (h + h[(-np.arange(nz)) % nz][:, (-np.arange(ny)) % ny][:, :, (-np.arange(nx)) % nx]) / 2
+    g = np.fft.rfftn(h, axes=(0, 1, 2)).real          # the library FFT, not the oracle
+    out, energy = oracle.convolve_real(x, g)
+    conv = _circular_convolution_brute(x, h)
+    assert oracle.rel_l2(out, x.size * conv) <= 1e-13
+    # sum_k G |Q|^2 = N sum_j x(j) (x (*) h)(j)
+    assert energy == pytest.approx(x.size * float(np.sum(x * conv)), rel=1e-12)
+
+
+def test_convolve_real_unit_multiplier_is_n_identity_and_parseval():
+    nz, ny, nx = 4, 5, 8
+    x = RNG.standard_normal((nz, ny, nx))
+    out, energy = oracle.convolve_real(x, np.ones((nz, ny, nx // 2 + 1)))
+    assert oracle.rel_l2(out / x.size, x) <= 1e-13
+    assert energy == pytest.approx(x.size * float(np.sum(x * x)), rel=1e-12)
+
+
+def test_convolve_real_dc_only_multiplier():
+    nz, ny, nx = 2, 3, 10
+    x = RNG.standard_normal((nz, ny, nx))
+    g = np.zeros((nz, ny, nx // 2 + 1))
+    g[0, 0, 0] = 2.5
+    out, energy = oracle.convolve_real(x, g)
+    np.testing.assert_allclose(out, np.full(x.shape, 2.5 * x.sum()), atol=1e-12)
+    assert energy == pytest.approx(2.5 * x.sum() ** 2, rel=1e-12)
+
+
+def test_half_weights_count_every_full_bin_once():
+    for nx in (4, 6, 16):
+        assert oracle.half_weights(nx).sum() == nx

@@ -114,3 +114,16 @@ def test_quantize_half_roundtrip(kind, bits):
     peak = np.maximum(np.abs(v.real), np.abs(v.imag)).max(axis=2, keepdims=True)
     err = np.maximum(np.abs(back.real - v.real), np.abs(back.imag - v.imag))
     assert np.all(err <= peak * 2.0 ** -bits)
+
+
+def test_pme_influence_is_even_finite_and_zero_at_dc():
+    nx, ny, nz = 12, 10, 8
+    g = synth.pme_influence(nx, ny, nz)
+    assert g.shape == (nz, ny, nx // 2 + 1)
+    assert np.all(np.isfinite(g)) and np.all(g >= 0) and g[0, 0, 0] == 0
+    # G(-k) = G(k): mirror ky and kz
+    mirror = g[(-np.arange(nz)) % nz][:, (-np.arange(ny)) % ny]
+    np.testing.assert_allclose(g, mirror, rtol=1e-14, atol=0)
+    # the B-spline modulus of the order-4 spline at the Nyquist frequency is 9
+    # (1 / |1/6 - 2/3 + 1/6|^2), and the Gaussian decays away from k = 0
+    assert g[0, 0, 1] > g[0, 0, 2] > g[0, 0, 3]
