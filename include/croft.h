@@ -22,8 +22,11 @@
  * Half-storage plans compute in FP32 and must be run through
  * croft_execute_scaled, which carries the exponents.
  *
- * Sizes: every axis length n satisfies 1 <= n <= 4096 and n = 2^a 3^b 5^c;
- * the grid holds at most 2^31 - 1 elements.  Others give
+ * Sizes: every axis length n satisfies 1 <= n <= 4096; the grid holds at
+ * most 2^31 - 1 elements.  Lengths of the form 2^a 3^b 5^c run mixed-radix
+ * Stockham kernels; any other length runs Bluestein's algorithm (a chirp
+ * convolution of power-of-two length m >= 2n - 1 held in LDS), which for
+ * CROFT_C128 limits such lengths to n <= 2048.  Others give
  * CROFT_ERR_UNSUPPORTED_SIZE.  Grids need not be cubic.
  *
  * Ownership: the caller owns `in`, `out` (device memory) and the exponent
@@ -71,7 +74,7 @@ enum croft_direction {
 enum croft_status {
     CROFT_SUCCESS = 0,
     CROFT_ERR_INVALID_VALUE = 1,    /* NULL or bad argument, overlapping buffers */
-    CROFT_ERR_UNSUPPORTED_SIZE = 2, /* axis length outside 1..4096 or not 2^a 3^b 5^c */
+    CROFT_ERR_UNSUPPORTED_SIZE = 2, /* axis length outside 1..4096, or a length no kernel covers */
     CROFT_ERR_UNSUPPORTED_DTYPE = 3,/* unknown dtype, or a call that does not fit it */
     CROFT_ERR_OUT_OF_MEMORY = 4,    /* a plan allocation failed */
     CROFT_ERR_HIP = 5,              /* a HIP runtime call or kernel launch failed */
@@ -237,6 +240,8 @@ struct croft_pass_info {
     int block_threads;
     long long blocks;    /* grid size of one launch over the whole grid */
     size_t lds_bytes;
+    int bluestein;       /* > 0: Bluestein's algorithm runs this pass with a convolution
+                            of this power-of-two length (radices describe that FFT) */
 };
 struct croft_plan_info {
     int nx, ny, nz, dtype, dir;

@@ -53,7 +53,7 @@ class PassInfo(ctypes.Structure):
                 ("radices", ctypes.c_int * CROFT_MAX_STAGES),
                 ("threads_per_line", ctypes.c_int), ("lines_per_block", ctypes.c_int),
                 ("block_threads", ctypes.c_int), ("blocks", ctypes.c_longlong),
-                ("lds_bytes", ctypes.c_size_t)]
+                ("lds_bytes", ctypes.c_size_t), ("bluestein", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -48,6 +48,7 @@ struct croft_plan {
     // per grid: the pass list of the plain schedule
     std::vector<std::vector<PassLaunch>> passes;
     std::map<int, void *> twiddles;  // length -> device table
+    std::map<int, std::pair<void *, void *>> bluestein;  // length -> (chirp, kernel DFT)
     int8_t *e1 = nullptr, *e2 = nullptr;  // half storage: exponents after x and y passes
     size_t work_bytes = 0;
     // real transforms: grids[0] holds the real dimensions; the backward
@@ -92,9 +93,8 @@ int check_dims(int nx, int ny, int nz) {
     const int d[3] = {nx, ny, nz};
     for (int a = 0; a < 3; ++a) {
         if (d[a] < 1) return fail(CROFT_ERR_INVALID_VALUE, "axis %d length %d < 1", a, d[a]);
-        if (!smooth_length(d[a]))
-            return fail(CROFT_ERR_UNSUPPORTED_SIZE,
-                        "axis %d length %d unsupported (need 1..%d of the form 2^a 3^b 5^c)", a, d[a],
+        if (d[a] > kMaxLength)
+            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "axis %d length %d unsupported (need 1..%d)", a, d[a],
                         kMaxLength);
     }
     if ((long long)nx * ny * nz > 0x7fffffffLL)
@@ -109,6 +109,15 @@ int check_dtype_dir(int dtype, int dir) {
         return fail(CROFT_ERR_INVALID_VALUE, "direction %d is neither CROFT_FORWARD (-1) nor CROFT_BACKWARD (+1)",
                     dir);
     return CROFT_SUCCESS;
+}
+
+int no_kernel(int n, int dtype) {
+    if (!smooth_length(n))
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE,
+                    "length %d needs Bluestein's algorithm, whose %d-point convolution does not fit in LDS for "
+                    "dtype %d (complex128: lengths up to 2048 only)",
+                    n, bluestein_length(n), dtype);
+    return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
 }
 
 // Static kernels address a thread's first element as a uniform 64-bit tile
@@ -146,9 +155,9 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
         int cand = 0, waves = 1;
         wisdom_lookup(n, p.kind, dtype, &cand, &waves);
         if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
-            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+            return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, p.kind, dtype, true, 0, &p.cfg))
-            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+            return no_kernel(n, dtype);
         p.cfg.grid_waves = waves;
         if (half) {
             ExpMap &m = p.em;
@@ -218,9 +227,9 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
         p.nw = axis == 1 ? g.nz : 1;
         wisdom_lookup(n, kStrided, dtype, &cand, &waves);
         if (!select_kernel(n, kStrided, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
-            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+            return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, kStrided, dtype, true, 0, &p.cfg))
-            return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
+            return no_kernel(n, dtype);
         p.cfg.grid_waves = waves;
         yz.push_back(p);
     }
@@ -249,10 +258,10 @@ int build_conv_passes(const Geometry &g, int dtype, int flags, std::vector<PassL
     c.hx = (long long)g.nx / 2 + 1;
     int cand = 0, waves = 1;
     wisdom_lookup(c.n, kConvZ, dtype, &cand, &waves);
-    if (!select_kernel(c.n, kConvZ, dtype, false, cand, &c.cfg))
-        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no fused multiply kernel for length %d", c.n);
-    if (!lane_offset_fits(c, dtype))
-        return fail(CROFT_ERR_UNSUPPORTED_SIZE, "grid too large for the fused multiply kernel");
+    const bool compiled = select_kernel(c.n, kConvZ, dtype, false, cand, &c.cfg);
+    if ((!compiled || !lane_offset_fits(c, dtype)) && !select_generic_conv(c.n, dtype, &c.cfg))
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE,
+                    "no fused multiply kernel for length %d (the fused axis needs a 2^a 3^b 5^c length)", c.n);
     c.cfg.grid_waves = waves;
     out->clear();
     for (PassLaunch pl : fwd) {
@@ -318,6 +327,10 @@ int check_exp_maps(const Geometry &g, const std::vector<PassLaunch> &ps) {
 void destroy_plan(croft_plan *p) {
     if (!p) return;
     for (auto &kv : p->twiddles) (void)hipFree(kv.second);
+    for (auto &kv : p->bluestein) {
+        (void)hipFree(kv.second.first);
+        (void)hipFree(kv.second.second);
+    }
     if (p->e1) (void)hipFree(p->e1);
     if (p->e2) (void)hipFree(p->e2);
     if (p->rwork) (void)hipFree(p->rwork);
@@ -399,11 +412,52 @@ int attach_resources(croft_plan *p) {
         *out = p->twiddles[n];
         return CROFT_SUCCESS;
     };
+    // Bluestein's chirp and kernel DFT of a length (convolution length m)
+    auto upload = [&](const std::vector<double> &v, void **out) -> int {
+        const size_t count = v.size() / 2;
+        const size_t bytes = count * compute_bytes(p->dtype);
+        if ((e = hipMalloc(out, bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            *out = nullptr;
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "Bluestein table: %s", hipGetErrorString(e));
+        }
+        p->work_bytes += bytes;
+        if (dbl) {
+            e = hipMemcpy(*out, v.data(), bytes, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> f(v.size());
+            for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+            e = hipMemcpy(*out, f.data(), bytes, hipMemcpyHostToDevice);
+        }
+        return e == hipSuccess ? CROFT_SUCCESS : fail_hip(e, "Bluestein table upload");
+    };
+    auto blue = [&](int n, int m, PassLaunch *pl) -> int {
+        if (!p->bluestein.count(n)) {
+            std::vector<double> c(2 * (size_t)n), b(2 * (size_t)m);
+            bluestein_tables_fp64(n, m, c.data(), b.data());
+            std::pair<void *, void *> t{nullptr, nullptr};
+            int rc = upload(c, &t.first);
+            if (rc == CROFT_SUCCESS) rc = upload(b, &t.second);
+            if (rc != CROFT_SUCCESS) {
+                if (t.first) (void)hipFree(t.first);
+                return rc;
+            }
+            p->bluestein[n] = t;
+        }
+        pl->chirp = p->bluestein[n].first;
+        pl->bhat = p->bluestein[n].second;
+        return CROFT_SUCCESS;
+    };
     for (auto &ps : p->passes) {
         for (PassLaunch &pl : ps) {
             int rc;
             pl.tw = nullptr;
-            if (pl.n > 1 && (rc = table(pl.n, &pl.tw)) != CROFT_SUCCESS) return rc;
+            if (pl.cfg.bluestein) {
+                if ((rc = table(pl.cfg.bluestein, &pl.tw)) != CROFT_SUCCESS) return rc;
+                if ((rc = blue(pl.n, pl.cfg.bluestein, &pl)) != CROFT_SUCCESS) return rc;
+            } else if (pl.n > 1 && (rc = table(pl.n, &pl.tw)) != CROFT_SUCCESS) {
+                return rc;
+            }
             if (pl.kind == kRealX && (rc = table(2 * pl.n, &pl.tw2)) != CROFT_SUCCESS) return rc;
             if ((rc = prepare_kernel(&pl.cfg)) != CROFT_SUCCESS) return rc;
         }
@@ -949,11 +1003,11 @@ int describe_impl(int nx, int ny, int nz, int dtype, int dir, int mode, char *bu
         const long long blocks = pass_tiles(pl);
         snprintf(line, sizeof line,
                  "pass %zu axis=%c n=%d kind=%s kernel=%s radices=%s stride=%lld lines=%lld T=%d L=%d block=%d "
-                 "blocks=%lld lds=%zu candidate=%d waves=%d\n",
+                 "blocks=%lld lds=%zu candidate=%d waves=%d bluestein=%d\n",
                  i, "xyz"[pl.axis], pl.n, kind_names[pl.kind],
-                 pl.cfg.generic ? "generic" : "static", rad.c_str(), pl.es,
+                 pl.cfg.bluestein ? "bluestein" : (pl.cfg.generic ? "generic" : "static"), rad.c_str(), pl.es,
                  !strided_kind(pl.kind) ? pl.nlines : pl.es * pl.nw, pl.cfg.threads_per_line, pl.cfg.lines,
-                 pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves);
+                 pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves, pl.cfg.bluestein);
         s += line;
     }
     if (len) {
@@ -1188,6 +1242,7 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
         pi.block_threads = pl.cfg.block;
         pi.blocks = pass_tiles(pl);
         pi.lds_bytes = pl.cfg.lds;
+        pi.bluestein = pl.cfg.bluestein;
     }
     info->elements = p->offsets.back();
     info->element_bytes = element_bytes(p->dtype);

@@ -326,6 +326,10 @@ struct PassArgs {
     const void *mul;
     double *partial;
     long long hx;
+    // Bluestein's algorithm (runtime kernel): chirp (n), kernel DFT (m), m
+    const void *chirp;
+    const void *bhat;
+    int m;
     int inverse;       // runtime-radix kernel only (static kernels take it as a template argument)
     // runtime-radix kernel only
     int n, T, L, S;

@@ -48,6 +48,8 @@ struct KernelConfig {
     size_t lds = 0;                  // dynamic LDS bytes per block
     int nstages = 0;
     int radix[kMaxStages] = {};
+    int bluestein = 0;   // > 0: Bluestein's algorithm with this power-of-two
+                         // convolution length (nstages / radix describe it)
     int resident = 0;    // blocks the device holds at once (0: unknown)
     int grid_waves = 1;  // static kernels: launch min(tiles, resident * grid_waves)
                          // blocks looping over tiles; 0 launches one block per tile
@@ -76,6 +78,8 @@ struct PassLaunch {
     const void *tw = nullptr;  // device twiddle table of length n (dtype's compute type)
     const void *tw2 = nullptr; // kRealX: device twiddle table of length 2 n
     ExpMap em;
+    const void *chirp = nullptr;  // Bluestein: exp(-pi i j^2 / n), j < n
+    const void *bhat = nullptr;   // Bluestein: DFT of the conjugate chirp kernel, / m
     int dir = 0;               // 0: the plan's direction; else CROFT_FORWARD / CROFT_BACKWARD
     long long hx = 0;          // kConvZ: spectrum elements per x-line
 };
@@ -99,6 +103,10 @@ long long pass_tiles(const PassLaunch &pl);
 hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *out,
                        const int8_t *in_exp, int8_t *out_exp, int inverse, hipStream_t stream,
                        const void *mul = nullptr, double *partial = nullptr);
+
+// The runtime-radix fused multiply pass (kConvZ) for a 2^a 3^b 5^c length
+// without a compiled one; false for other lengths and for half storage.
+bool select_generic_conv(int n, int dtype, KernelConfig *cfg);
 
 // Blocks a pass launches (persistent grids loop over the tiles).
 long long pass_blocks(const PassLaunch &pl);
@@ -141,5 +149,12 @@ int factorize(int n, int *radix);  // returns stage count, 0 if unsupported
 // Forward twiddles w[m] = exp(-2 pi i m / n), m < n, computed in FP64 with
 // octant symmetry, written as interleaved doubles (2n values).
 void twiddles_fp64(int n, double *out);
+// Bluestein's tables for length n and convolution length m >= 2n - 1:
+// chirp[j] = exp(-pi i j^2 / n), j < n (2n doubles), and bhat = the m-point
+// DFT of b, b[i] = b[m - i] = conj chirp[i] for i < n (zero elsewhere),
+// divided by m (2m doubles).  All in FP64.
+void bluestein_tables_fp64(int n, int m, double *chirp, double *bhat);
+// Smallest power of two >= 2n - 1.
+int bluestein_length(int n);
 
 }  // namespace croft

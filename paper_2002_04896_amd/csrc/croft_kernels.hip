@@ -138,6 +138,216 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
     }
 }
 
+// Stages of the plan in a.radix over LDS lines of length len, ping-ponging
+// between two buffers; returns the buffer that holds the result.
+template <typename R, int KIND>
+__device__ cx<R> *run_stages(const PassArgs &a, cx<R> *src, cx<R> *dst, const cx<R> *tw, int len, int L, int l,
+                             int t, int T, bool active) {
+    int Ns = 1;
+    for (int s = 0; s < a.S; ++s) {
+        const int rad = a.radix[s];
+        if (active) {
+            switch (rad) {
+                case 2: generic_stage<2, R, KIND>(src, dst, tw, len, L, l, t, T, Ns); break;
+                case 3: generic_stage<3, R, KIND>(src, dst, tw, len, L, l, t, T, Ns); break;
+                case 4: generic_stage<4, R, KIND>(src, dst, tw, len, L, l, t, T, Ns); break;
+                case 5: generic_stage<5, R, KIND>(src, dst, tw, len, L, l, t, T, Ns); break;
+                case 8: generic_stage<8, R, KIND>(src, dst, tw, len, L, l, t, T, Ns); break;
+                default: generic_stage<16, R, KIND>(src, dst, tw, len, L, l, t, T, Ns); break;
+            }
+        }
+        Ns *= rad;
+        cx<R> *tmp = src;
+        src = dst;
+        dst = tmp;
+        __syncthreads();
+    }
+    return src;
+}
+
+// ------------------------------------------------------------ Bluestein
+// Lengths with a prime factor above 5 (Bluestein 1970): with
+// c[j] = exp(-pi i j^2 / n),
+//   X[k] = c[k] sum_j (x[j] c[j]) conj(c[k - j]),
+// a circular convolution of length m (a power of two >= 2n - 1) done as
+// m-point FFTs in LDS: forward FFT of the chirped, zero-padded line, product
+// with the kernel's DFT (precomputed, divided by m), then the inverse FFT as
+// swap(DFT(swap(.))) and the final chirp.  a.S / a.radix / a.tw describe
+// the m-point FFT.  Same line geometry, exponents and inverse-by-swap as the
+// runtime-radix kernel.
+template <class St, int KIND>
+__global__ void __launch_bounds__(256) fft_bluestein(const PassArgs a) {
+    using R = typename St::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, m = a.m, T = a.T, L = a.L;
+    cx<R> *buf0 = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *buf1 = buf0 + (size_t)L * m;
+    unsigned *red = reinterpret_cast<unsigned *>(buf1 + (size_t)L * m);
+    const cx<R> *tw = reinterpret_cast<const cx<R> *>(a.tw);
+    const cx<R> *ch = reinterpret_cast<const cx<R> *>(a.chirp);
+    const cx<R> *bh = reinterpret_cast<const cx<R> *>(a.bhat);
+    const int tid = threadIdx.x;
+    const int l = KIND == kContiguous ? tid / T : tid % L;
+    const int t = KIND == kContiguous ? tid % T : tid / L;
+    const bool active = tid < T * L;
+    long long q, w;
+    if (KIND == kContiguous) {
+        q = (long long)blockIdx.x * L + l;
+        w = 0;
+    } else {
+        q = ((long long)blockIdx.x % a.ntiles) * L + l;
+        w = (long long)blockIdx.x / a.ntiles;
+    }
+    const bool valid = active && q < (KIND == kContiguous ? a.nlines : a.es);
+    const long long es = KIND == kContiguous ? 1 : a.es;
+    const long long base = KIND == kContiguous ? q * n : q + w * a.es * n;
+    const bool inv = a.inverse != 0;
+    int ebase = 0;
+    if constexpr (St::kHalf) {
+        const ExpMap &mp = a.em;
+        ebase = (int)((q % mp.qmod) * mp.a0 + (q / mp.qmod) * mp.a1 + w * mp.a2);
+        if (active && t == 0) red[l] = 0u;
+    }
+    // chirped line, zero-padded to m
+    if (active) {
+        for (int e = t; e < m; e += T) {
+            cx<R> v = {R(0), R(0)};
+            if (valid && e < n) {
+                int ex = 0;
+                if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + a.em.a3 * e] : 0;
+                v = St::decode(St::fetch(a.in, base + es * e), ex);
+                if (inv) v = {v.y, v.x};
+                v = cmul(v, ch[e]);
+            }
+            buf0[glds<KIND>(l, e, m, L)] = v;
+        }
+    }
+    __syncthreads();
+    cx<R> *r = run_stages<R, KIND>(a, buf0, buf1, tw, m, L, l, t, T, active);
+    // product with the kernel's DFT, swapped: the next forward FFT then gives
+    // the unnormalised inverse once swapped back
+    if (active) {
+        for (int e = t; e < m; e += T) {
+            cx<R> &v = r[glds<KIND>(l, e, m, L)];
+            const cx<R> p = cmul(v, bh[e]);
+            v = {p.y, p.x};
+        }
+    }
+    __syncthreads();
+    cx<R> *o = run_stages<R, KIND>(a, r, r == buf0 ? buf1 : buf0, tw, m, L, l, t, T, active);
+    // X[k] = c[k] swap(o[k]); every thread rewrites only the entries it reads later
+    if (active) {
+        for (int e = t; e < n; e += T) {
+            cx<R> &v = o[glds<KIND>(l, e, m, L)];
+            v = cmul(cx<R>{v.y, v.x}, ch[e]);
+        }
+    }
+    int ex = 0;
+    if constexpr (St::kHalf) {
+        float mx = 0.0f;
+        if (active)
+            for (int e = t; e < n; e += T) {
+                const cx<R> v = o[glds<KIND>(l, e, m, L)];
+                mx = fmaxf(mx, fmaxf(fabsf((float)v.x), fabsf((float)v.y)));
+            }
+        if (active) atomicMax(&red[l], __float_as_uint(mx));
+        __syncthreads();
+        if (active) ex = line_exponent(__uint_as_float(red[l]));
+        if (valid && t == 0 && a.out_exp) {
+            const ExpMap &mp = a.em;
+            a.out_exp[(q % mp.qmod) * mp.b0 + (q / mp.qmod) * mp.b1 + w * mp.b2] = (int8_t)ex;
+        }
+    }
+    if (valid) {
+        for (int e = t; e < n; e += T) {
+            cx<R> v = o[glds<KIND>(l, e, m, L)];
+            if (inv) v = {v.y, v.x};
+            St::store(a.out, base + es * e, v, ex);
+        }
+    }
+}
+
+// ------------------------------------------------------ fused multiply (any length)
+// The fused forward FFT / multiply / inverse FFT pass of a convolution plan for
+// 2^a 3^b 5^c lengths without a compiled fused kernel: strided lines, one tile
+// per block, the runtime-radix stages twice, the product (and the energy
+// terms, as in the compiled kernel) in between.
+template <class St>
+__global__ void __launch_bounds__(256) fft_generic_conv(const PassArgs a) {
+    using R = typename St::R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, T = a.T, L = a.L;
+    cx<R> *buf0 = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *buf1 = buf0 + (size_t)L * n;
+    const cx<R> *tw = reinterpret_cast<const cx<R> *>(a.tw);
+    const R *G = reinterpret_cast<const R *>(a.mul);
+    const int tid = threadIdx.x;
+    const int l = tid % L;
+    const int t = tid / L;
+    const bool active = tid < T * L;
+    const long long q = ((long long)blockIdx.x % a.ntiles) * L + l;
+    const long long w = (long long)blockIdx.x / a.ntiles;
+    const bool valid = active && q < a.es;
+    const long long es = a.es;
+    const long long base = q + w * es * n;
+    if (active) {
+        for (int e = t; e < n; e += T) {
+            cx<R> v = {R(0), R(0)};
+            if (valid) v = St::decode(St::fetch(a.in, base + es * e), 0);
+            buf0[glds<kStrided>(l, e, n, L)] = v;
+        }
+    }
+    __syncthreads();
+    cx<R> *r = run_stages<R, kStrided>(a, buf0, buf1, tw, n, L, l, t, T, active);
+    double acc = 0.0;
+    if (valid) {
+        const long long kx = q % a.hx;
+        const double wgt = (kx == 0 || kx == a.hx - 1) ? 1.0 : 2.0;
+        for (int e = t; e < n; e += T) {
+            cx<R> &v = r[glds<kStrided>(l, e, n, L)];
+            const R gv = G[base + es * e];
+            const double m2 = (double)v.x * v.x + (double)v.y * v.y;
+            acc = fma(wgt * (double)gv, m2, acc);
+            v = cx<R>{v.y * gv, v.x * gv};  // the product, swapped for the inverse
+        }
+    }
+    __syncthreads();
+    cx<R> *o = run_stages<R, kStrided>(a, r, r == buf0 ? buf1 : buf0, tw, n, L, l, t, T, active);
+    if (valid) {
+        for (int e = t; e < n; e += T) {
+            const cx<R> v = o[glds<kStrided>(l, e, n, L)];
+            St::store(a.out, base + es * e, cx<R>{v.y, v.x}, 0);
+        }
+    }
+    __syncthreads();
+    double *sum = reinterpret_cast<double *>(smem);  // the line buffers are free now
+    const int B = blockDim.x;
+    sum[tid] = acc;
+    __syncthreads();
+    for (int h = 1; h < B; h *= 2) {
+        if ((tid & (2 * h - 1)) == 0 && tid + h < B) sum[tid] += sum[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) a.partial[blockIdx.x] = sum[0];
+}
+
+const void *bluestein_func(int kind, int dtype) {
+    if (kind == kContiguous) {
+        switch (dtype) {
+            case kC64: return reinterpret_cast<const void *>(&fft_bluestein<StC64, kContiguous>);
+            case kC128: return reinterpret_cast<const void *>(&fft_bluestein<StC128, kContiguous>);
+            case kC16F: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<false>, kContiguous>);
+            default: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<true>, kContiguous>);
+        }
+    }
+    switch (dtype) {
+        case kC64: return reinterpret_cast<const void *>(&fft_bluestein<StC64, kStrided>);
+        case kC128: return reinterpret_cast<const void *>(&fft_bluestein<StC128, kStrided>);
+        case kC16F: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<false>, kStrided>);
+        default: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<true>, kStrided>);
+    }
+}
+
 const std::vector<Entry> &table() {
     static const std::vector<Entry> t = [] {
         std::vector<Entry> v;
@@ -206,6 +416,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
             cfg->func = pick->func[0];
             cfg->func_inv = pick->func[1];
             cfg->generic = false;
+            cfg->bluestein = 0;
             cfg->candidate = pick->cand;
             cfg->threads_per_line = pick->T;
             cfg->lines = pick->L;
@@ -217,9 +428,36 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
         }
     }
     if (kind == kRealX || kind == kConvZ) return false;  // compiled configurations only
-    const RPlan p = make_rplan(n);
-    if (p.S < 0) return false;
     const int cb = dtype == kC128 ? 16 : 8;                      // compute bytes
+    if (make_rplan(n).S < 0) {
+        // Bluestein: two LDS lines of the m-point convolution per line
+        const int m = bluestein_length(n);
+        const RPlan pm = make_rplan(m);
+        const size_t per_line = 2 * (size_t)m * cb + 4;
+        int lds_lines = (int)((160 * 1024) / per_line);
+        if (lds_lines < 1 || pm.S < 0) return false;
+        int T = m / pm.rmax;
+        if (T > 256) T = 256;
+        if (T < 1) T = 1;
+        int L = kind == kContiguous ? 256 / T : std::max(1, std::min(256 / T, 128 / (int)element_bytes(dtype)));
+        if (L > lds_lines) L = lds_lines;
+        if (L < 1) L = 1;
+        int p2 = 1;
+        while (p2 * 2 <= L) p2 *= 2;
+        L = p2;
+        cfg->func = cfg->func_inv = bluestein_func(kind, dtype);
+        cfg->generic = true;
+        cfg->bluestein = m;
+        cfg->candidate = 0;
+        cfg->threads_per_line = T;
+        cfg->lines = L;
+        cfg->block = ((T * L + 63) / 64) * 64;
+        cfg->lds = (size_t)L * per_line;
+        cfg->nstages = pm.S;
+        for (int s = 0; s < pm.S; ++s) cfg->radix[s] = pm.r[s];
+        return true;
+    }
+    const RPlan p = make_rplan(n);
     const int sb = (int)element_bytes(dtype);                    // storage bytes
     int T = n / p.rmax;
     if (T < 1) T = 1;
@@ -242,6 +480,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
     L = p2;
     cfg->func = cfg->func_inv = generic_func(kind, dtype);
     cfg->generic = true;
+    cfg->bluestein = 0;
     cfg->candidate = 0;
     cfg->threads_per_line = T;
     cfg->lines = L;
@@ -273,6 +512,9 @@ hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *ou
     a.out = out;
     a.tw = pl.tw;
     a.tw2 = pl.tw2;
+    a.chirp = pl.chirp;
+    a.bhat = pl.bhat;
+    a.m = pl.cfg.bluestein;
     a.mul = mul;
     a.partial = partial;
     a.hx = pl.hx;
@@ -301,6 +543,15 @@ hipError_t launch_pass(const PassLaunch &pl, int dtype, const void *in, void *ou
 hipError_t launch_sum_partials(const double *partial, int n, double *energy, hipStream_t stream) {
     void *args[] = {&partial, &n, &energy};
     return hipLaunchKernel(reinterpret_cast<const void *>(&sum_partials), dim3(1), dim3(256), args, 0, stream);
+}
+
+bool select_generic_conv(int n, int dtype, KernelConfig *cfg) {
+    if ((dtype != kC64 && dtype != kC128) || make_rplan(n).S < 0) return false;
+    if (!select_kernel(n, kStrided, dtype, true, 0, cfg) || cfg->bluestein) return false;
+    cfg->func = cfg->func_inv = dtype == kC64 ? reinterpret_cast<const void *>(&fft_generic_conv<StC64>)
+                                              : reinterpret_cast<const void *>(&fft_generic_conv<StC128>);
+    cfg->lds = std::max(cfg->lds, (size_t)cfg->block * sizeof(double));  // the block sum reuses the line buffers
+    return true;
 }
 
 }  // namespace croft

@@ -1,6 +1,8 @@
 // croft_plan.cpp -- host-side planning helpers: supported lengths, radix
-// factorisation and the FP64 twiddle generator.
+// factorisation, the FP64 twiddle generator and Bluestein's tables.
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "croft_internal.h"
 
@@ -67,6 +69,66 @@ void twiddles_fp64(int n, double *out) {
         }
         out[2 * m] = C;
         out[2 * m + 1] = -S;
+    }
+}
+
+int bluestein_length(int n) {
+    int m = 1;
+    while (m < 2 * n - 1) m *= 2;
+    return m;
+}
+
+// Bluestein (1970): with j k = (j^2 + k^2 - (k - j)^2) / 2,
+//   sum_j x[j] exp(-2 pi i j k / n) = c[k] sum_j (x[j] c[j]) conj(c[k - j]),
+// c[j] = exp(-pi i j^2 / n): a circular convolution of length m >= 2n - 1
+// once the kernel conj(c[i]), |i| < n, is wrapped into [0, m).
+void bluestein_tables_fp64(int n, int m, double *chirp, double *bhat) {
+    // c[j] = exp(-2 pi i r / (2n)), r = j^2 mod 2n: the length-2n twiddle table
+    std::vector<double> w(4 * (size_t)n);
+    twiddles_fp64(2 * n, w.data());
+    for (int j = 0; j < n; ++j) {
+        const long long r = ((long long)j * j) % (2LL * n);
+        chirp[2 * j] = w[2 * r];
+        chirp[2 * j + 1] = w[2 * r + 1];
+    }
+    std::vector<double> re(m, 0.0), im(m, 0.0);
+    for (int i = 0; i < n; ++i) {
+        re[i] = chirp[2 * i];
+        im[i] = -chirp[2 * i + 1];
+        if (i > 0) {
+            re[m - i] = chirp[2 * i];
+            im[m - i] = -chirp[2 * i + 1];
+        }
+    }
+    // iterative radix-2 FFT (decimation in time), exp(-2 pi i ...) sign
+    for (int i = 1, j = 0; i < m; ++i) {
+        int bit = m >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            std::swap(re[i], re[j]);
+            std::swap(im[i], im[j]);
+        }
+    }
+    std::vector<double> tw(2 * (size_t)m);
+    twiddles_fp64(m, tw.data());
+    for (int len = 2; len <= m; len *= 2) {
+        const int step = m / len;
+        for (int i = 0; i < m; i += len) {
+            for (int k = 0; k < len / 2; ++k) {
+                const double wr = tw[2 * (size_t)k * step], wi = tw[2 * (size_t)k * step + 1];
+                const int a = i + k, b = i + k + len / 2;
+                const double xr = re[b] * wr - im[b] * wi, xi = re[b] * wi + im[b] * wr;
+                re[b] = re[a] - xr;
+                im[b] = im[a] - xi;
+                re[a] += xr;
+                im[a] += xi;
+            }
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        bhat[2 * i] = re[i] / m;
+        bhat[2 * i + 1] = im[i] / m;
     }
 }
 

@@ -28,12 +28,30 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("dims,msg", [
-    ((0, 4, 4), "< 1"), ((4, -2, 4), "< 1"), ((7, 4, 4), "unsupported"),
-    ((4, 4, 4097), "unsupported"), ((4, 4, 8192), "unsupported"), ((14, 4, 4), "unsupported"),
+    ((0, 4, 4), "< 1"), ((4, -2, 4), "< 1"), ((4097, 4, 4), "unsupported"),
+    ((4, 4, 4097), "unsupported"), ((4, 4, 8192), "unsupported"), ((4, 5000, 4), "unsupported"),
 ])
 def test_create_rejects_bad_sizes(dims, msg):
     with pytest.raises(ValueError, match=msg):
         croft.croft_plan_create(*dims)
+
+
+@pytest.mark.parametrize("n", [7, 11, 13, 14, 97, 1009, 2039, 4093])
+def test_lengths_with_large_prime_factors_use_bluestein(n):
+    _, passes = parse_describe(croft.croft_plan_describe(n, 6, 5))
+    p = passes[0]
+    m = int(p["bluestein"])
+    assert p["kernel"] == "bluestein" and m >= 2 * n - 1 and m & (m - 1) == 0 and m < 4 * n
+    assert int(p["lds"]) <= 160 * 1024 and int(p["block"]) <= 256
+    _, passes = parse_describe(croft.croft_plan_describe(6, n, 5, croft.CROFT_C16F))
+    assert passes[1]["kernel"] == "bluestein"
+
+
+def test_bluestein_complex128_limit():
+    _, passes = parse_describe(croft.croft_plan_describe(2039, 2, 1, croft.CROFT_C128))
+    assert passes[0]["kernel"] == "bluestein" and passes[0]["bluestein"] == "4096"
+    with pytest.raises(ValueError, match="Bluestein"):
+        croft.croft_plan_describe(2053, 2, 1, croft.CROFT_C128)
 
 
 def test_create_rejects_bad_dtype_and_direction():
@@ -51,7 +69,7 @@ def test_create_rejects_bad_dtype_and_direction():
 
 def test_batched_create_rejects_bad_grids():
     with pytest.raises(ValueError, match="grid 1"):
-        croft.croft_plan_create_batched([(8, 8, 8), (8, 7, 8)])
+        croft.croft_plan_create_batched([(8, 8, 8), (8, 4097, 8)])
     with pytest.raises(ValueError, match="C64 or"):
         croft.croft_plan_create_batched([(8, 8, 8)], croft.CROFT_C16F)
     with pytest.raises(ValueError, match="count"):
@@ -206,7 +224,7 @@ def test_describe_real_supported_lengths_fit_the_device(nx, dt):
 @pytest.mark.parametrize("dims,dt,msg", [
     ((7, 4, 4), croft.CROFT_C64, "even nx"), ((2, 4, 4), croft.CROFT_C64, "even nx"),
     ((8194, 4, 4), croft.CROFT_C64, "even nx"), ((162, 4, 4), croft.CROFT_C64, "no real x kernel"),
-    ((16, 7, 4), croft.CROFT_C64, "unsupported"), ((16, 4, 4), croft.CROFT_C16F, "CROFT_C64 or CROFT_C128"),
+    ((16, 4097, 4), croft.CROFT_C64, "unsupported"), ((16, 4, 4), croft.CROFT_C16F, "CROFT_C64 or CROFT_C128"),
 ])
 def test_real_plans_reject_bad_arguments(dims, dt, msg):
     with pytest.raises(ValueError, match=msg):
@@ -234,7 +252,7 @@ def test_describe_convolution_fuses_y_when_nz_is_one():
 
 
 @pytest.mark.parametrize("dims,dt,msg", [
-    ((16, 1, 1), croft.CROFT_C64, "ny > 1 or nz > 1"), ((16, 4, 45), croft.CROFT_C64, "no fused"),
+    ((16, 1, 1), croft.CROFT_C64, "ny > 1 or nz > 1"), ((16, 4, 7), croft.CROFT_C64, "no fused"),
     ((15, 4, 4), croft.CROFT_C64, "even nx"), ((16, 4, 4), croft.CROFT_C16B, "CROFT_C64 or CROFT_C128"),
 ])
 def test_convolution_plans_reject_bad_arguments(dims, dt, msg):
@@ -255,3 +273,10 @@ def test_static_kernels_are_only_used_where_lane_offsets_fit_32_bits():
         assert p["kernel"] == "generic" or (span + 1) * 16 <= 0xFFFFFFFF
     _, passes = parse_describe(croft.croft_plan_describe(4096, 4096, 100, croft.CROFT_C64))
     assert passes[2]["kernel"] == "static"
+
+
+def test_describe_convolution_uncompiled_fused_length_runs_the_runtime_kernel():
+    _, passes = parse_describe(croft.croft_plan_describe_convolution(32, 20, 24))
+    assert passes[2]["kind"] == "fused" and passes[2]["kernel"] == "generic"
+    _, passes = parse_describe(croft.croft_plan_describe_convolution(32, 20, 64))
+    assert passes[2]["kind"] == "fused" and passes[2]["kernel"] == "static"

@@ -362,3 +362,10 @@ def test_convolve_real_dc_only_multiplier():
 def test_half_weights_count_every_full_bin_once():
     for nx in (4, 6, 16):
         assert oracle.half_weights(nx).sum() == nx
+
+
+@pytest.mark.parametrize("nzyx", [(7, 11, 13), (2, 3, 97), (17, 1, 5)], ids=str)
+def test_matches_numpy_on_lengths_with_large_prime_factors(nzyx):
+    x = rand_grid(*nzyx)
+    assert oracle.rel_l2(oracle.dft3d(x, -1), np.fft.fftn(x)) <= 1e-13
+    assert oracle.rel_l2(oracle.dft3d(x, 1), np.fft.ifftn(x) * x.size) <= 1e-13
