@@ -504,8 +504,8 @@ int attach_resources(croft_plan *p) {
 }
 
 // CROFT_MEASURE: time every compiled configuration of each distinct pass
-// (candidate x persistent grid size) on scratch buffers, keep the fastest and
-// record it as wisdom.
+// (candidate x persistent grid size, forward and inverse) on scratch buffers,
+// keep the fastest and record it as wisdom.
 int measure_passes(croft_plan *p) {
     size_t maxN = 0, maxE = 1;
     for (const Geometry &g : p->grids) {
@@ -563,25 +563,32 @@ int measure_passes(croft_plan *p) {
                 }
                 if (!fits) continue;
                 if ((rc = prepare_kernel(&cfg)) != CROFT_SUCCESS) break;
+                // a choice serves both directions (the wisdom key has none), and
+                // the two instantiations of a configuration can differ in speed
+                // (e.g. one spills registers), so both are timed
+                const int ndir = cfg.func_inv != cfg.func ? 2 : 1;
                 for (int waves : {1, 2, 4, 0}) {
                     float total = 0.f;
                     for (const PassLaunch *q : same) {
                         PassLaunch t = *q;
                         t.cfg = cfg;
                         t.cfg.grid_waves = waves;
-                        float best_rep = 1e30f;
-                        e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0, a, p->partial);  // warm-up
-                        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                            float ms = 0.f;
-                            e = hipEventRecord(t0, 0);
-                            if (e == hipSuccess) e = launch_pass(t, p->dtype, a, b, ei, eo, inv, 0, a, p->partial);
-                            if (e == hipSuccess) e = hipEventRecord(t1, 0);
-                            if (e == hipSuccess) e = hipEventSynchronize(t1);
-                            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-                            best_rep = std::min(best_rep, ms);
+                        for (int d = 0; d < ndir && e == hipSuccess; ++d) {
+                            const int iv = ndir == 2 ? d : (int)inv;
+                            float best_rep = 1e30f;
+                            e = launch_pass(t, p->dtype, a, b, ei, eo, iv, 0, a, p->partial);  // warm-up
+                            for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                                float ms = 0.f;
+                                e = hipEventRecord(t0, 0);
+                                if (e == hipSuccess) e = launch_pass(t, p->dtype, a, b, ei, eo, iv, 0, a, p->partial);
+                                if (e == hipSuccess) e = hipEventRecord(t1, 0);
+                                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                                best_rep = std::min(best_rep, ms);
+                            }
+                            total += best_rep;
                         }
                         if (e != hipSuccess) break;
-                        total += best_rep;
                     }
                     if (e != hipSuccess) {
                         rc = fail_hip(e, "autotune launch");

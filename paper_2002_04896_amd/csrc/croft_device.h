@@ -838,6 +838,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
             static_stage<Cfg, St, kContiguous, false, 0, kToLds>(a, lds, tws, red, t, l, c, lane, 1, cur, ex);
             __syncthreads();
             cx<R> *out = reinterpret_cast<cx<R> *>(a.out) + q0 * H;
+#pragma unroll 1
             for (int i = tid; i < nl * H; i += Cfg::kBlock) {
                 const int ln = i / H, k = i - ln * H;
                 const cx<R> A = at(ln, k == M ? 0 : k);
@@ -850,6 +851,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
             }
         } else {
             const cx<R> *X = reinterpret_cast<const cx<R> *>(a.in) + q0 * H;
+#pragma unroll 1
             for (int i = tid; i < nl * H; i += Cfg::kBlock) {
                 const int ln = i / H, k = i - ln * H;
                 const cx<R> v = X[i];
@@ -859,6 +861,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
             __syncthreads();
             // pairs (k, M - k), 0 <= k <= M/2, merged in place; k = 0 pairs with X[M]
             constexpr int P = M / 2 + 1;
+#pragma unroll 1
             for (int i = tid; i < nl * P; i += Cfg::kBlock) {
                 const int ln = i / P, k = i - ln * P;
                 const int r = M - k;
@@ -926,19 +929,44 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_conv_z(const PassArgs a) {
         int ex = 0;
         Tile<Cfg, St> cur;
         fetch_tile<Cfg, St, kStrided, false>(a, c, t, lane, es, cur);
+        // the multiplier of this thread's elements (e = t + k T); with few
+        // elements per thread it is loaded now, so that the loads are in
+        // flight during the forward stages (wide tiles load it afterwards, as
+        // holding it across the stages would spill)
+        constexpr int T = B / L;
+        constexpr int E = (N + T - 1) / T;
+        constexpr bool kEarly = E <= 8;
+        const R *g = G + c.tbase + l;
+        R gv[E];
+        if (kEarly && c.valid) {
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int e = t + k * T;
+                gv[k] = e < N ? g[(long long)e * es] : R(0);
+            }
+        }
         static_stage<Cfg, St, kStrided, false, 0, kToLds>(a, lds, tws, red, t, l, c, lane, es, cur, ex);
         __syncthreads();
         if (c.valid) {
             // element (line l, position e) sits at LDS index e L + l
             const long long kx = c.q % a.hx;
             const double wgt = (kx == 0 || kx == a.hx - 1) ? 1.0 : 2.0;
-            const R *g = G + c.tbase + l;
-            for (int e = t; e < N; e += B / L) {
-                cx<R> &v = lds[e * L + l];
-                const R gv = g[(long long)e * es];
-                const double m2 = (double)v.x * v.x + (double)v.y * v.y;
-                acc = fma(wgt * (double)gv, m2, acc);
-                v = cx<R>{v.x * gv, v.y * gv};
+            if (!kEarly) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int e = t + k * T;
+                    gv[k] = e < N ? g[(long long)e * es] : R(0);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int e = t + k * T;
+                if (e < N) {
+                    cx<R> &v = lds[e * L + l];
+                    const double m2 = (double)v.x * v.x + (double)v.y * v.y;
+                    acc = fma(wgt * (double)gv[k], m2, acc);
+                    v = cx<R>{v.x * gv[k], v.y * gv[k]};
+                }
             }
         }
         __syncthreads();

@@ -153,8 +153,10 @@ def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
 
 def test_builtin_wisdom_picks_wide_strided_tiles(tmp_path, monkeypatch):
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512)
-    assert [p["candidate"] for p in passes][1:] == ["2", "2"]
-    assert passes[1]["L"] == "32" and passes[1]["T"] == "32"
+    # the measured choice: 32-line (256-byte row) tiles of 16 threads x 32
+    # elements, which run the forward and the inverse without spilling
+    assert [p["candidate"] for p in passes][1:] == ["4", "4"]
+    assert passes[1]["L"] == "32" and passes[1]["T"] == "16"
 
 
 def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
