@@ -250,11 +250,13 @@ __device__ __forceinline__ unsigned short float_to_f16_bits(float f) {
 __device__ __forceinline__ float bf16_bits_to_float(unsigned short b) {
     return __uint_as_float(static_cast<unsigned>(b) << 16);
 }
-// Round to nearest, ties to even, on the upper 16 bits of the binary32 value.
-__device__ __forceinline__ unsigned short float_to_bf16_bits(float f) {
-    const unsigned u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);
-    return static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+// Two binary32 values to two bfloat16 (first in the low half), rounded to
+// nearest, ties to even: one v_cvt_pk_bf16_f32 on gfx950.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned floats_to_bf16x2_bits(float lo, float hi) {
+    const f32x2 w = {lo, hi};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(w, bf16x2));
 }
 
 template <bool BF>
@@ -276,8 +278,9 @@ struct StHalf {
     // stores v * 2^-e, rounded to nearest even
     static __device__ __forceinline__ unsigned encode(cx<R> v, int e) {
         const float re = ldexpf(v.x, -e), im = ldexpf(v.y, -e);
-        const unsigned lo = BF ? float_to_bf16_bits(re) : float_to_f16_bits(re);
-        const unsigned hi = BF ? float_to_bf16_bits(im) : float_to_f16_bits(im);
+        if constexpr (BF) return floats_to_bf16x2_bits(re, im);
+        const unsigned lo = float_to_f16_bits(re);
+        const unsigned hi = float_to_f16_bits(im);
         return lo | (hi << 16);
     }
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int e) {
