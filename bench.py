@@ -216,6 +216,29 @@ def measure_conv(torch, np, croft, synth, pme, steps):
     return res
 
 
+def measure_large(torch, np, croft, pme, steps):
+    """A 1024^3 complex64 PME grid (8 GiB), forward, out of place: the 512^3
+    PME grid repeated 2 x 2 x 2 on the device (a periodic charge grid of the
+    same density; generating a fresh 1024^3 grid on the host takes a minute)."""
+    n = 1024
+    half = torch.from_numpy(pme).cuda()
+    d_in = half.repeat(2, 2, 2)
+    qtot = 8.0 * float(half.real.to(torch.float64).sum())
+    del half
+    d_out = torch.empty_like(d_in)
+    plan = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+    info = croft.croft_plan_info(plan)
+    ms, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out), steps, 2, 3)
+    croft.croft_plan_destroy(plan)
+    dc = d_out[0, 0, 0].item()
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    return {"ms": ms, "GFLOPs": flops_5nlogn(n ** 3) / ms / 1e6,
+            "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
+            "effective_frac_of_8TBps": info["algorithmic_bytes"] / ms / 1e6 / HBM_PEAK_GBPS, "pass_ms": pm,
+            "dc_minus_total_charge": dc.real - qtot}
+
+
 def measure_forms(torch, np, croft, synth, steps):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
@@ -369,6 +392,7 @@ def main():
         torch.cuda.empty_cache()
         line["forms"] = measure_real(torch, np, croft, x, max(10, args.steps // 2))
         line["forms"]["convolution"] = measure_conv(torch, np, croft, synth, x, max(10, args.steps // 2))
+        line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5))
         line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2)))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, n)
