@@ -322,3 +322,91 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def _check_tensor(t, name, shape, dtype_name):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if str(t.dtype).replace("torch.", "") != dtype_name:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype_name}")
+    if not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError(f"{name}: must be a contiguous device tensor")
+
+
+class RealPlan:
+    """Owning wrapper of croft_plan_create_real: ``RealPlan(nx, ny, nz, dtype, dir)``.
+
+    Forward: ``plan(x, y)`` with x real (nz, ny, nx) and y complex
+    (nz, ny, nx//2 + 1); backward the other way round.  float32/complex64 for
+    CROFT_C64, float64/complex128 for CROFT_C128.
+    """
+
+    _REAL = {CROFT_C64: "float32", CROFT_C128: "float64"}
+    _CPLX = {CROFT_C64: "complex64", CROFT_C128: "complex128"}
+
+    def __init__(self, nx, ny, nz, dtype=CROFT_C64, dir=CROFT_FORWARD, flags=0):
+        self.real_shape = (nz, ny, nx)
+        self.spec_shape = (nz, ny, nx // 2 + 1)
+        self.dtype, self.dir = dtype, dir
+        self.handle = croft_plan_create_real(nx, ny, nz, dtype, dir, flags)
+
+    def __call__(self, inp, out, stream=None):
+        r = (self.real_shape, self._REAL[self.dtype])
+        c = (self.spec_shape, self._CPLX[self.dtype])
+        (si, di), (so, do) = (r, c) if self.dir == CROFT_FORWARD else (c, r)
+        _check_tensor(inp, "in", si, di)
+        _check_tensor(out, "out", so, do)
+        croft_execute(self.handle, inp, out, stream)
+        return out
+
+    def info(self) -> dict:
+        return croft_plan_info(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            croft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class ConvolutionPlan:
+    """Owning wrapper of croft_plan_create_convolution:
+    ``ConvolutionPlan(nx, ny, nz, dtype)``; ``plan(x, g, out, energy=None)``
+    with x and out real (nz, ny, nx), g real (nz, ny, nx//2 + 1) and energy a
+    one-element float64 device tensor or None."""
+
+    _REAL = {CROFT_C64: "float32", CROFT_C128: "float64"}
+
+    def __init__(self, nx, ny, nz, dtype=CROFT_C64, flags=0):
+        self.real_shape = (nz, ny, nx)
+        self.spec_shape = (nz, ny, nx // 2 + 1)
+        self.dtype = dtype
+        self.handle = croft_plan_create_convolution(nx, ny, nz, dtype, flags)
+
+    def __call__(self, inp, mul, out, energy=None, stream=None):
+        _check_tensor(inp, "in", self.real_shape, self._REAL[self.dtype])
+        _check_tensor(mul, "mul", self.spec_shape, self._REAL[self.dtype])
+        _check_tensor(out, "out", self.real_shape, self._REAL[self.dtype])
+        if energy is not None:
+            _check_tensor(energy, "energy", (1,), "float64")
+        croft_execute_convolution(self.handle, inp, mul, out, energy, stream)
+        return out
+
+    def info(self) -> dict:
+        return croft_plan_info(self.handle)
+
+    def destroy(self):
+        if self.handle:
+            croft_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

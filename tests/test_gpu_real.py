@@ -189,3 +189,32 @@ def test_pme_512_forward_and_backward_lines():
     got = np.stack([back[z, y] for y, z in kyz])
     assert oracle.rel_l2(got, oracle.irdft3d_lines(h, n, kyz)) <= TOL[C64]
     log("done")
+
+
+def test_python_wrappers_check_shapes_and_run():
+    nx, ny, nz = 32, 12, 10
+    x = torch.from_numpy(real_grid((nx, ny, nz), 15, C64)).cuda()
+    h = torch.empty((nz, ny, nx // 2 + 1), dtype=torch.complex64, device="cuda")
+    back = torch.empty_like(x)
+    f = croft.RealPlan(nx, ny, nz, C64, FWD)
+    b = croft.RealPlan(nx, ny, nz, C64, BWD)
+    f(x, h)
+    b(h, back)
+    torch.cuda.synchronize()
+    assert oracle.rel_l2(back.cpu().numpy() / x.numel(), x.cpu().numpy()) <= 10 * TOL[C64]
+    with pytest.raises(ValueError, match="shape"):
+        f(x, torch.empty((nz, ny, nx), dtype=torch.complex64, device="cuda"))
+    with pytest.raises(ValueError, match="dtype"):
+        b(h, torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda"))
+    g = torch.ones((nz, ny, nx // 2 + 1), dtype=torch.float32, device="cuda")
+    e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    conv = croft.ConvolutionPlan(nx, ny, nz, C64)
+    out = conv(x, g, torch.empty_like(x), e)
+    torch.cuda.synchronize()
+    xs = x.cpu().numpy().astype(np.float64)
+    assert oracle.rel_l2(out.cpu().numpy() / x.numel(), xs) <= 10 * TOL[C64]
+    assert abs(e.item() - x.numel() * float(np.sum(xs * xs))) <= 1e-5 * x.numel() * float(np.sum(xs * xs))
+    with pytest.raises(ValueError, match="mul"):
+        conv(x, torch.ones((nz, ny, nx), dtype=torch.float32, device="cuda"), torch.empty_like(x))
+    for p in (f, b, conv):
+        p.destroy()
