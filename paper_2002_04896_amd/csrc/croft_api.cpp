@@ -132,7 +132,7 @@ bool lane_offset_fits(const PassLaunch &p, int dtype) {
 // The pass list of one grid, without device resources (twiddle pointers are
 // filled in later).  Half storage always runs all three axes, so that every
 // pass re-scales its lines and the output exponents are per z-line.
-int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch> *out) {
+int build_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<PassLaunch> *out) {
     const int dims[3] = {g.nx, g.ny, g.nz};
     const long long N = (long long)g.nx * g.ny * g.nz;
     const bool half = is_half(dtype);
@@ -153,7 +153,7 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
             p.nw = N / (p.es * n);
         }
         int cand = 0, waves = 1;
-        wisdom_lookup(n, p.kind, dtype, &cand, &waves);
+        wisdom_lookup(n, p.kind, dtype, dir, &cand, &waves);
         if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
             return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, p.kind, dtype, true, 0, &p.cfg))
@@ -199,7 +199,11 @@ int build_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch
 // the real x pass on the half-length complex view, and the complex y and z
 // passes on the (nx/2 + 1) x ny x nz half spectrum.  Forward runs x, y, z;
 // backward z, y, x.
-int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<PassLaunch> *out) {
+// tune_dir: the direction the wisdom lookup assumes (0 when the passes run
+// in both directions, as in a convolution plan).
+int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<PassLaunch> *out,
+                      int tune_dir = 2) {
+    if (tune_dir == 2) tune_dir = dir;
     out->clear();
     const int m = g.nx / 2;
     const long long h = (long long)m + 1;  // spectrum elements per x-line
@@ -210,7 +214,7 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
     xp.es = 1;
     xp.nlines = (long long)g.ny * g.nz;
     int cand = 0, waves = 1;
-    wisdom_lookup(m, kRealX, dtype, &cand, &waves);
+    wisdom_lookup(m, kRealX, dtype, tune_dir, &cand, &waves);
     if (!select_kernel(m, kRealX, dtype, false, cand, &xp.cfg))
         return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no real x kernel for nx = %d (half length %d)", g.nx, m);
     xp.cfg.grid_waves = waves;
@@ -225,7 +229,7 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
         p.es = axis == 1 ? h : h * g.ny;
         p.nlines = p.es;
         p.nw = axis == 1 ? g.nz : 1;
-        wisdom_lookup(n, kStrided, dtype, &cand, &waves);
+        wisdom_lookup(n, kStrided, dtype, tune_dir, &cand, &waves);
         if (!select_kernel(n, kStrided, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
             return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, kStrided, dtype, true, 0, &p.cfg))
@@ -248,7 +252,7 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
 // multiply / inverse pass, then the backward passes in reverse order.
 int build_conv_passes(const Geometry &g, int dtype, int flags, std::vector<PassLaunch> *out) {
     std::vector<PassLaunch> fwd;
-    int rc = build_real_passes(g, dtype, CROFT_FORWARD, flags, &fwd);
+    int rc = build_real_passes(g, dtype, CROFT_FORWARD, flags, &fwd, 0);
     if (rc != CROFT_SUCCESS) return rc;
     if (fwd.size() < 2)
         return fail(CROFT_ERR_UNSUPPORTED_SIZE, "convolution plans need ny > 1 or nz > 1");
@@ -257,7 +261,7 @@ int build_conv_passes(const Geometry &g, int dtype, int flags, std::vector<PassL
     c.kind = kConvZ;
     c.hx = (long long)g.nx / 2 + 1;
     int cand = 0, waves = 1;
-    wisdom_lookup(c.n, kConvZ, dtype, &cand, &waves);
+    wisdom_lookup(c.n, kConvZ, dtype, 0, &cand, &waves);
     const bool compiled = select_kernel(c.n, kConvZ, dtype, false, cand, &c.cfg);
     if ((!compiled || !lane_offset_fits(c, dtype)) && !select_generic_conv(c.n, dtype, &c.cfg))
         return fail(CROFT_ERR_UNSUPPORTED_SIZE,
@@ -710,7 +714,7 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
     for (size_t i = 0; i < grids.size(); ++i) {
         const int rc = conv   ? build_conv_passes(grids[i], dtype, flags, &p->passes[i])
                        : real ? build_real_passes(grids[i], dtype, dir, flags, &p->passes[i])
-                              : build_passes(grids[i], dtype, flags, &p->passes[i]);
+                              : build_passes(grids[i], dtype, dir, flags, &p->passes[i]);
         if (rc != CROFT_SUCCESS) {
             delete p;
             return nullptr;
@@ -987,7 +991,7 @@ int describe_impl(int nx, int ny, int nz, int dtype, int dir, int mode, char *bu
     std::vector<PassLaunch> ps;
     rc = mode == 2 ? build_conv_passes(g, dtype, 0, &ps)
          : real    ? build_real_passes(g, dtype, dir, 0, &ps)
-                   : build_passes(g, dtype, 0, &ps);
+                   : build_passes(g, dtype, dir, 0, &ps);
     if (rc != CROFT_SUCCESS) return rc;
     if (is_half(dtype) && (rc = check_exp_maps(g, ps)) != CROFT_SUCCESS) return rc;
     static const char *names[] = {"c64", "c128", "c16f", "c16b"};

@@ -140,7 +140,9 @@ hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t l
                         const void *in, void *out, hipStream_t stream);
 
 // ---- wisdom (croft_tune.cpp) ----
-bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves);
+// dir: -1 forward, +1 backward, 0 a pass that runs in both directions (the
+// forward-only built-in choices apply to -1 only).
+bool wisdom_lookup(int n, int kind, int dtype, int dir, int *cand, int *waves);
 void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist);
 
 // ---- planner (croft_plan.cpp) ----

@@ -6,8 +6,8 @@
 // this process are kept in memory; when the environment variable CROFT_WISDOM
 // names a file, plans also read it and CROFT_MEASURE plans append to it.
 // File format, one choice per line:  n kind dtype candidate waves
-// Lookup order: the CROFT_WISDOM file, choices measured in this process, the
-// built-in table below (measured on an MI355X with CROFT_MEASURE on cubic
+// Lookup order: the CROFT_WISDOM file, choices measured in this process, for
+// forward plans the forward-only built-in choices, the built-in table below (measured on an MI355X with CROFT_MEASURE on cubic
 // grids; kinds 2 and 3, the real x pass and the fused multiply pass, on real
 // and convolution plans of cubic grids), then candidate 0 with one resident
 // wave.
@@ -56,6 +56,14 @@ const Builtin kBuiltin[] = {
     {512, 0, 3, 2, 4}, {512, 1, 3, 4, 1}, {1024, 0, 3, 2, 4}, {1024, 1, 3, 5, 1},
 };
 
+// Forward-only choices, looked up before the table above by forward plans:
+// where the best configuration for both directions together is not the best
+// forward one (512 strided complex64: the 1024-thread wide tile is the
+// fastest forward but spills in its inverse).
+const Builtin kBuiltinForward[] = {
+    {512, 1, 0, 2, 1},
+};
+
 std::mutex g_mu;
 std::map<std::tuple<int, int, int>, std::pair<int, int>> g_mem;
 
@@ -77,7 +85,7 @@ bool read_file(const char *path, int n, int kind, int dtype, int *cand, int *wav
 }
 }  // namespace
 
-bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves) {
+bool wisdom_lookup(int n, int kind, int dtype, int dir, int *cand, int *waves) {
     std::lock_guard<std::mutex> lk(g_mu);
     const char *path = std::getenv("CROFT_WISDOM");
     if (path && *path && read_file(path, n, kind, dtype, cand, waves)) return true;
@@ -86,6 +94,15 @@ bool wisdom_lookup(int n, int kind, int dtype, int *cand, int *waves) {
         *cand = it->second.first;
         *waves = it->second.second;
         return true;
+    }
+    if (dir == -1) {
+        for (const Builtin &b : kBuiltinForward) {
+            if (b.n == n && b.kind == kind && b.dtype == dtype) {
+                *cand = b.cand;
+                *waves = b.waves;
+                return true;
+            }
+        }
     }
     for (const Builtin &b : kBuiltin) {
         if (b.n == n && b.kind == kind && b.dtype == dtype) {

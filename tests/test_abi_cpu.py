@@ -152,9 +152,13 @@ def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
 
 
 def test_builtin_wisdom_picks_wide_strided_tiles(tmp_path, monkeypatch):
+    # measured choices, all with 32-line (256-byte row) tiles: forward plans
+    # take the 1024-thread tile (32 x 16 elements), fastest forward; backward
+    # plans the 512-thread tile (16 x 32), whose inverse does not spill
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512)
-    # the measured choice: 32-line (256-byte row) tiles of 16 threads x 32
-    # elements, which run the forward and the inverse without spilling
+    assert [p["candidate"] for p in passes][1:] == ["2", "2"]
+    assert passes[1]["L"] == "32" and passes[1]["T"] == "32"
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, 0, 1)
     assert [p["candidate"] for p in passes][1:] == ["4", "4"]
     assert passes[1]["L"] == "32" and passes[1]["T"] == "16"
 
