@@ -247,6 +247,15 @@ def measure_forms(torch, np, croft, synth, steps):
     n = 512
     N = n ** 3
     v = synth.normal_c((n, n, n), seed=5)
+    # the complex64 transform of the input before quantisation, for the
+    # information of the error it carries into the 16-bit forms
+    d_orig = torch.from_numpy(v.astype(np.complex64)).cuda()
+    orig_out = torch.empty_like(d_orig)
+    oplan = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+    croft.croft_execute(oplan, d_orig, orig_out)
+    torch.cuda.synchronize()
+    croft.croft_plan_destroy(oplan)
+    del d_orig
     for name, dt, kind in (("c16f", croft.CROFT_C16F, "f16"), ("c16b", croft.CROFT_C16B, "bf16")):
         data, e = synth.quantize_half(v, kind)
         tdt = torch.float16 if kind == "f16" else torch.bfloat16
@@ -270,12 +279,15 @@ def measure_forms(torch, np, croft, synth, steps):
         croft.croft_plan_destroy(cplan)
         got = (d_out.float()[..., 0] + 1j * d_out.float()[..., 1]) * torch.pow(2.0, e_out.float())[None, :, :]
         err = rel_l2_dev(torch, got, c_out)
+        err_orig = rel_l2_dev(torch, got, orig_out)
         out[name] = {"ms": ms, "GFLOPs": flops_5nlogn(N) / ms / 1e6,
                      "effective_GBps": info["algorithmic_bytes"] / ms / 1e6, "pass_ms": pm,
-                     "c64_ms": ms_c64, "speedup_vs_c64": ms_c64 / ms, "rel_l2_vs_c64": err}
+                     "c64_ms": ms_c64, "speedup_vs_c64": ms_c64 / ms, "rel_l2_vs_c64": err,
+                     "rel_l2_vs_c64_of_unquantised_input": err_orig}
         del d_in, d_out, vals, c_out, got
         torch.cuda.empty_cache()
-    del v
+    del v, orig_out
+    torch.cuda.empty_cache()
     # batched: 64 uneven PME grids
     dims = synth.batch_dims(4)
     grids = [synth.pme_grid(int(a), int(b), int(c), seed=400 + i)[0] for i, (a, b, c) in enumerate(dims)]

@@ -147,7 +147,6 @@ def test_half_storage_512(dtype):
     log(f"half {kind} 512^3: generate")
     v = synth.normal_c((n, n, n), seed=5)
     data, e = synth.quantize_half(v, kind)
-    del v
     d_in = torch.from_numpy(data.view(np.int16)).cuda().view(HALF_TORCH[dtype])
     d_out = torch.empty_like(d_in)
     e_in = torch.from_numpy(e).cuda()
@@ -175,3 +174,8 @@ def test_half_storage_512(dtype):
     err = oracle.rel_l2(got, ref)
     log(f"{kind} rel-L2 vs oracle of the stored input: {err:.3e}")
     assert err <= TOL[dtype]
+    # for information: against the oracle of the input before quantisation
+    # (adds the input's own 16-bit rounding)
+    err_orig = oracle.rel_l2(got, oracle.dft3d_lines(v, kyz, -1))
+    log(f"{kind} rel-L2 vs oracle of the unquantised input: {err_orig:.3e}")
+    assert err_orig <= 2 * TOL[dtype]
