@@ -294,21 +294,26 @@ def measure_forms(torch, np, croft, synth, steps):
     flat = np.concatenate([g.ravel() for g in grids]).astype(np.complex64)
     d_in = torch.from_numpy(flat).cuda()
     d_out = torch.empty_like(d_in)
-    plan = croft.croft_plan_create_batched([tuple(int(t) for t in d) for d in dims], croft.CROFT_C64,
-                                           croft.CROFT_FORWARD)
     fl = sum(flops_5nlogn(int(a) * int(b) * int(c)) for a, b, c in dims)
-    for _ in range(3):
-        croft.croft_execute_batched(plan, d_in, d_out)
-    torch.cuda.synchronize()
     a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a_.record()
-    for _ in range(steps):
-        croft.croft_execute_batched(plan, d_in, d_out)
-    b_.record()
-    torch.cuda.synchronize()
-    ms = a_.elapsed_time(b_) / steps
-    info = croft.croft_plan_info(plan)
-    croft.croft_plan_destroy(plan)
+
+    def time_batched(flags, dst):
+        plan = croft.croft_plan_create_batched([tuple(int(t) for t in d) for d in dims], croft.CROFT_C64,
+                                               croft.CROFT_FORWARD, flags)
+        for _ in range(3):
+            croft.croft_execute_batched(plan, d_in, dst)
+        torch.cuda.synchronize()
+        a_.record()
+        for _ in range(steps):
+            croft.croft_execute_batched(plan, d_in, dst)
+        b_.record()
+        torch.cuda.synchronize()
+        info = croft.croft_plan_info(plan)
+        croft.croft_plan_destroy(plan)
+        return a_.elapsed_time(b_) / steps, info
+    ms, info = time_batched(0, d_out)
+    d_coop = torch.empty_like(d_in)
+    ms_coop, _ = time_batched(croft.CROFT_PERSISTENT, d_coop)
     # the same grids as separate plain plans on one stream
     plans = [croft.croft_plan_create(int(a), int(b), int(c), croft.CROFT_C64, croft.CROFT_FORWARD)
              for a, b, c in dims]
@@ -333,7 +338,9 @@ def measure_forms(torch, np, croft, synth, steps):
     out["batched_64"] = {"ms": ms, "GFLOPs": fl / ms / 1e6, "elements": int(flat.size),
                          "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
                          "plain_calls_ms": ms_plain, "speedup_vs_plain_calls": ms_plain / ms,
-                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref))}
+                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref)),
+                         "cooperative_ms": ms_coop,
+                         "cooperative_bitwise_equal": bool(torch.equal(d_coop, d_out))}
     return out
 
 

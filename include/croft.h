@@ -89,11 +89,11 @@ enum croft_flags {
     CROFT_MEASURE = 1,        /* time candidate configurations at create (autotune) */
     CROFT_FORCE_GENERIC = 2,  /* use the runtime-radix kernels for every pass */
     CROFT_NO_WISDOM = 4,      /* MEASURE: neither read nor write the wisdom file */
-    CROFT_PERSISTENT = 8      /* batched plans: one persistent launch for every pass of every
-                                 grid (work handed out by an atomic ticket in pass order, a grid's
-                                 pass waiting for its previous pass), instead of one launch per pass.
-                                 Currently disabled: plan creation with this flag fails with
-                                 CROFT_ERR_UNSUPPORTED_DTYPE. */
+    CROFT_PERSISTENT = 8      /* batched plans: one cooperative launch for every pass of every
+                                 grid (all blocks resident, looping over the tiles of pass 0, a
+                                 grid-wide barrier, pass 1, a barrier, pass 2) instead of one
+                                 launch per pass.  Issued directly on the stream, not through the
+                                 plan's graph; same results bit for bit. */
 };
 
 /* Create a plan for one nx x ny x nz transform (the paper's problem statement,
@@ -150,8 +150,8 @@ int croft_plan_batched_offsets(croft_plan_t plan, size_t *elem_offsets);
 
 /* Run every transform of a batched plan (one from croft_plan_create_batched;
  * others give CROFT_ERR_INVALID_VALUE): one launch per axis pass covering
- * all grids (or one persistent launch with CROFT_PERSISTENT), replayed from a
- * HIP graph captured on first use for the given (in, out, stream).  Grids
+ * all grids, replayed from a HIP graph captured on first use for the given
+ * (in, out, stream) -- or, with CROFT_PERSISTENT, one cooperative launch.  Grids
  * whose lengths the batched kernels do not compile (any outside 48, 60, 64,
  * 72, 80, 96, 100, 128) run with launches of their own inside the same graph.
  * Same in/out rules as croft_execute. */
@@ -218,13 +218,6 @@ int croft_execute_convolution(croft_plan_t plan, const void *in, const void *mul
 
 /* Dry run of croft_plan_create_convolution (no GPU). */
 int croft_plan_describe_convolution(int nx, int ny, int nz, int dtype, char *buf, size_t len);
-
-/* Waits for the device and reports whether a persistent batched launch of
- * this plan ever had to give up waiting for a previous pass (device_status
- * 1; the results of that execute are then invalid) -- 0 otherwise and for
- * plans without such a launch.  Synchronising; a diagnostic, not for hot
- * paths. */
-int croft_plan_status(croft_plan_t plan, int *device_status);
 
 /* Description of a plan, filled by croft_plan_info. */
 #define CROFT_MAX_PASSES 8

@@ -37,7 +37,7 @@ EXPORTED = (
     "croft_plan_create", "croft_plan_create_ex", "croft_execute", "croft_execute_scaled",
     "croft_plan_destroy", "croft_last_error", "croft_plan_create_batched",
     "croft_plan_batched_offsets", "croft_execute_batched", "croft_plan_info",
-    "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read", "croft_plan_status",
+    "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read",
     "croft_plan_create_real", "croft_plan_describe_real", "croft_plan_create_convolution",
     "croft_execute_convolution", "croft_plan_describe_convolution",
 )
@@ -121,8 +121,6 @@ def load():
     lib.croft_execute_convolution.restype = i
     lib.croft_plan_describe_convolution.argtypes = [i, i, i, i, ctypes.c_char_p, ctypes.c_size_t]
     lib.croft_plan_describe_convolution.restype = i
-    lib.croft_plan_status.argtypes = [p, ctypes.POINTER(ctypes.c_int)]
-    lib.croft_plan_status.restype = i
     lib.croft_plan_profile.argtypes = [p, i]
     lib.croft_plan_profile.restype = i
     lib.croft_plan_profile_read.argtypes = [p, ctypes.POINTER(ctypes.c_double), i,
@@ -244,13 +242,6 @@ def croft_plan_describe_convolution(nx, ny, nz, dtype=CROFT_C64) -> str:
     buf = ctypes.create_string_buffer(8192)
     _check(load().croft_plan_describe_convolution(nx, ny, nz, dtype, buf, len(buf)))
     return buf.value.decode()
-
-
-def croft_plan_status(plan) -> int:
-    """Device status word of the plan's persistent batched launch (0 = fine)."""
-    v = ctypes.c_int(0)
-    _check(load().croft_plan_status(plan, ctypes.byref(v)))
-    return v.value
 
 
 def croft_plan_profile(plan, enable: bool) -> None:

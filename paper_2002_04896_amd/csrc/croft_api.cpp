@@ -68,9 +68,7 @@ struct croft_plan {
     int bbegin[4] = {0, 0, 0, 0};      // segments of pass p: [bbegin[p], bbegin[p + 1])
     long long btiles[3] = {0, 0, 0};   // tiles of pass p
     size_t blds[3] = {0, 0, 0};
-    unsigned *bcounters = nullptr;     // persistent launch: ticket + per-segment done counts
-    unsigned *bstatus = nullptr;       // persistent launch: set if a wait gave up
-    int bresident = 0;                 // persistent launch: blocks held at once
+    int bresident = 0;                 // cooperative launch: blocks the device holds at once
     std::vector<size_t> loose;  // grids run with their own launches
     // batched form: graph cache
     hipGraphExec_t graph = nullptr;
@@ -346,7 +344,6 @@ void destroy_plan(croft_plan *p) {
     if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     if (p->bitems) (void)hipFree(p->bitems);
-    if (p->bcounters) (void)hipFree(p->bcounters);
     for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
     for (auto &v : p->prof)
         for (auto &pr : v) {
@@ -621,7 +618,7 @@ int measure_passes(croft_plan *p) {
 }
 
 // Batched plans: the segment table of the batched kernels (one segment per
-// grid and pass, pass by pass), and the persistent launch's counters.
+// grid and pass, pass by pass), and the cooperative launch's grid size.
 int build_batch_tables(croft_plan *p) {
     const bool usable = (p->dtype == CROFT_C64 || p->dtype == CROFT_C128) && !(p->flags & CROFT_FORCE_GENERIC);
     const size_t ib = batch_item_bytes();
@@ -633,8 +630,6 @@ int build_batch_tables(croft_plan *p) {
         (ok ? grids : p->loose).push_back(g);
     }
     std::vector<char> host;
-    std::vector<int> seg_of(p->grids.size() * 3, -1);  // (grid, pass) -> segment index
-    std::vector<long long> seg_total;
     int nseg = 0;
     for (int i = 0; i < 3; ++i) {
         p->bbegin[i] = nseg;
@@ -653,13 +648,10 @@ int build_batch_tables(croft_plan *p) {
                 ntiles = (pl.es + bc.lines - 1) / bc.lines;
                 total = ntiles * pl.nw;
             }
-            const int dep = i > 0 ? seg_of[g * 3 + i - 1] : -1;
             host.resize(host.size() + ib);
             batch_item_fill(host.data() + host.size() - ib, (long long)p->offsets[g], p->btiles[i], pl.es,
-                            pl.kind == kContiguous ? pl.nlines : pl.es, pl.nw, ntiles, total, pl.tw, code, i == 0,
-                            dep, dep >= 0 ? seg_total[dep] : 0);
-            seg_of[g * 3 + i] = nseg++;
-            seg_total.push_back(total);
+                            pl.kind == kContiguous ? pl.nlines : pl.es, pl.nw, ntiles, total, pl.tw, code, i == 0);
+            ++nseg;
             p->btiles[i] += total;
             p->blds[i] = std::max(p->blds[i], bc.lds);
         }
@@ -667,30 +659,31 @@ int build_batch_tables(croft_plan *p) {
     p->bbegin[3] = nseg;
     if (!nseg) return CROFT_SUCCESS;
     hipError_t e = hipMalloc(&p->bitems, host.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&p->bcounters, sizeof(unsigned) * (size_t)(nseg + 2));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(CROFT_ERR_OUT_OF_MEMORY, "batch tables: %s", hipGetErrorString(e));
     }
-    p->bstatus = p->bcounters + nseg + 1;
-    p->work_bytes += host.size() + sizeof(unsigned) * (size_t)(nseg + 2);
+    p->work_bytes += host.size();
     if ((e = hipMemcpy(p->bitems, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail_hip(e, "batch table upload");
-    if ((e = hipMemset(p->bcounters, 0, sizeof(unsigned) * (size_t)(nseg + 2))) != hipSuccess)
-        return fail_hip(e, "batch counters");
     const size_t lds = std::max({p->blds[0], p->blds[1], p->blds[2]});
+    int nb = 1 << 30;
     for (int inv = 0; inv < 2; ++inv) {
-        const void *fs[2] = {batch_kernel(p->dtype, inv), batch_persistent_kernel(p->dtype, inv)};
+        const void *fs[2] = {batch_kernel(p->dtype, inv), batch_coop_kernel(p->dtype, inv)};
         for (const void *f : fs) {
             if (lds > 65536 &&
                 (e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
                 return fail_hip(e, "LDS attribute");
         }
+        // the cooperative grid must fit at once: the smaller occupancy of the
+        // two directions, at the largest LDS any pass needs
+        int n = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs[1], 256, lds)) != hipSuccess)
+            return fail_hip(e, "occupancy query");
+        nb = std::min(nb, n);
     }
-    int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_persistent_kernel(p->dtype, 0), 256, lds);
-    if (e != hipSuccess) return fail_hip(e, "occupancy query");
-    p->bresident = std::max(1, nb) * std::max(1, device_cus());
+    if (nb < 1) return fail(CROFT_ERR_INTERNAL, "the cooperative batched kernel cannot be resident");
+    p->bresident = nb * std::max(1, device_cus());
     return CROFT_SUCCESS;
 }
 
@@ -888,7 +881,6 @@ int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
     const size_t eb = element_bytes(p->dtype);
     const int inv = p->dir == CROFT_BACKWARD;
     const size_t ib = batch_item_bytes();
-    const long long tb[4] = {0, p->btiles[0], p->btiles[0] + p->btiles[1], p->btiles[0] + p->btiles[1] + p->btiles[2]};
     const int nlaunch = (p->flags & CROFT_PERSISTENT) ? (p->bbegin[3] > 0 ? 1 : 0) : 3;
     for (int i = 0; i < nlaunch; ++i) {
         const int n = p->bbegin[i + 1] - p->bbegin[i];
@@ -903,9 +895,9 @@ int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
         hipError_t e;
         if (p->flags & CROFT_PERSISTENT) {
             const size_t lds = std::max({p->blds[0], p->blds[1], p->blds[2]});
-            const int blocks = (int)std::min<long long>(p->bresident, tb[3]);
-            e = launch_batch_persistent(p->bitems, p->bbegin, tb, p->bcounters, (unsigned)(p->bbegin[3] + 1),
-                                        p->bstatus, blocks, lds, p->dtype, inv, in, out, s);
+            const long long most = std::max({p->btiles[0], p->btiles[1], p->btiles[2]});
+            const int blocks = (int)std::min<long long>(p->bresident, most);
+            e = launch_batch_coop(p->bitems, p->bbegin, p->btiles, blocks, lds, p->dtype, inv, in, out, s);
         } else {
             e = launch_batch((const char *)p->bitems + (size_t)p->bbegin[i] * ib, n, p->btiles[i], p->blds[i],
                              p->dtype, inv, in, out, s);
@@ -1135,13 +1127,7 @@ croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, in
         fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
         return nullptr;
     }
-    if (flags & CROFT_PERSISTENT) {
-        // The single persistent launch (blocks waiting on other blocks' done
-        // counts) stalled in its first device test and is switched off until
-        // the cause is established; batched plans use one launch per pass.
-        fail(CROFT_ERR_UNSUPPORTED_DTYPE, "CROFT_PERSISTENT is disabled in this version");
-        return nullptr;
-    }
+
     std::vector<Geometry> grids;
     long long total = 0;
     for (int i = 0; i < count; ++i) {
@@ -1187,6 +1173,9 @@ int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t
         p->prof.push_back(std::move(rec));
         return rc;
     }
+    // the cooperative launch is issued directly (one launch already), the
+    // per-pass launches through the captured graph
+    if (p->flags & CROFT_PERSISTENT) return run_batch(p, in, out, stream, nullptr);
     if (!p->graph || p->graph_in != in || p->graph_out != out || p->graph_stream != stream) {
         if (p->graph) {
             (void)hipGraphExecDestroy(p->graph);
@@ -1284,17 +1273,6 @@ int croft_plan_describe_real(int nx, int ny, int nz, int dtype, int dir, char *b
 
 int croft_plan_describe_convolution(int nx, int ny, int nz, int dtype, char *buf, size_t len) {
     return describe_impl(nx, ny, nz, dtype, CROFT_FORWARD, 2, buf, len);
-}
-
-int croft_plan_status(croft_plan_t p, int *device_status) {
-    if (!p || !device_status) return fail(CROFT_ERR_INVALID_VALUE, "NULL argument");
-    *device_status = 0;
-    if (!p->bstatus) return CROFT_SUCCESS;
-    unsigned v = 0;
-    const hipError_t e = hipMemcpy(&v, p->bstatus, sizeof v, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return fail_hip(e, "status read");
-    *device_status = (int)v;
-    return CROFT_SUCCESS;
 }
 
 int croft_plan_profile(croft_plan_t p, int enable) {

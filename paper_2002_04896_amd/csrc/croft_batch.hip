@@ -1,6 +1,7 @@
 // croft_batch.hip -- the batched form: one launch per axis pass covering the
-// tiles of every grid in a batch (compiled lengths 48, 60, 64, 72, 80, 96,
-// 100, 128; complex64 and complex128).
+// tiles of every grid in a batch, or one cooperative launch for all passes
+// (compiled lengths 48, 60, 64, 72, 80, 96, 100, 128; complex64 and
+// complex128).
 #include <hip/hip_runtime.h>
 
 #include "croft_device.h"
@@ -10,12 +11,6 @@ namespace croft {
 using namespace dev;
 
 namespace {
-// Zeroes the ticket and done counters before a persistent launch (a kernel,
-// not a memset, so that the launch can be captured in a graph).
-__global__ void __launch_bounds__(256) batch_reset(unsigned *counters, unsigned n, unsigned *status) {
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counters[i] = 0u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0u;
-}
 }  // namespace
 
 int batch_code(int n, int kind) {
@@ -80,45 +75,33 @@ hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t l
 
 size_t batch_item_bytes() { return sizeof(BatchItem); }
 
-const void *batch_persistent_kernel(int dtype, int inverse) {
+const void *batch_coop_kernel(int dtype, int inverse) {
     if (dtype == kC64)
-        return inverse ? reinterpret_cast<const void *>(&fft_batch_persistent<StC64, true>)
-                       : reinterpret_cast<const void *>(&fft_batch_persistent<StC64, false>);
+        return inverse ? reinterpret_cast<const void *>(&fft_batch_coop<StC64, true>)
+                       : reinterpret_cast<const void *>(&fft_batch_coop<StC64, false>);
     if (dtype == kC128)
-        return inverse ? reinterpret_cast<const void *>(&fft_batch_persistent<StC128, true>)
-                       : reinterpret_cast<const void *>(&fft_batch_persistent<StC128, false>);
+        return inverse ? reinterpret_cast<const void *>(&fft_batch_coop<StC128, true>)
+                       : reinterpret_cast<const void *>(&fft_batch_coop<StC128, false>);
     return nullptr;
 }
 
-hipError_t launch_batch_persistent(const void *items, const int item_begin[4], const long long tile_begin[4],
-                                   unsigned *counters, unsigned ncounters, unsigned *status, int blocks,
-                                   size_t lds, int dtype, int inverse, const void *in, void *out,
-                                   hipStream_t stream) {
-    if (tile_begin[3] <= 0) return hipSuccess;
-    if (tile_begin[3] > 0xffffffffLL) return hipErrorInvalidConfiguration;
-    void *rargs[] = {&counters, &ncounters, &status};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void *>(&batch_reset), dim3(1), dim3(256), rargs, 0,
-                                   stream);
-    if (e != hipSuccess) return e;
-    BatchPersistentArgs b;
+hipError_t launch_batch_coop(const void *items, const int item_begin[4], const long long tiles[3], int blocks,
+                             size_t lds, int dtype, int inverse, const void *in, void *out, hipStream_t stream) {
+    if (tiles[0] + tiles[1] + tiles[2] <= 0) return hipSuccess;
+    if (blocks < 1) return hipErrorInvalidConfiguration;
+    BatchCoopArgs b;
     b.items = reinterpret_cast<const BatchItem *>(items);
-    for (int i = 0; i < 4; ++i) {
-        b.item_begin[i] = item_begin[i];
-        b.tile_begin[i] = tile_begin[i];
-    }
-    b.counters = counters;
-    b.status = status;
+    for (int i = 0; i < 4; ++i) b.item_begin[i] = item_begin[i];
+    for (int i = 0; i < 3; ++i) b.tiles[i] = tiles[i];
     b.in = in;
     b.out = out;
-    b.spin_limit = 1u << 24;
     void *args[] = {&b};
-    return hipLaunchKernel(batch_persistent_kernel(dtype, inverse), dim3((unsigned)blocks), dim3(256), args, lds,
-                           stream);
+    return hipLaunchCooperativeKernel(batch_coop_kernel(dtype, inverse), dim3((unsigned)blocks), dim3(256), args,
+                                      (unsigned)lds, stream);
 }
 
 void batch_item_fill(void *dst, long long offset, long long tile_begin, long long es, long long nlines,
-                     long long nw, long long ntiles, long long total, const void *tw, int code, int from_in,
-                     int dep, long long dep_total) {
+                     long long nw, long long ntiles, long long total, const void *tw, int code, int from_in) {
     BatchItem it;
     it.offset = offset;
     it.tile_begin = tile_begin;
@@ -130,8 +113,6 @@ void batch_item_fill(void *dst, long long offset, long long tile_begin, long lon
     it.tw = tw;
     it.code = code;
     it.from_in = from_in;
-    it.dep = dep;
-    it.dep_total = dep_total;
     *reinterpret_cast<BatchItem *>(dst) = it;
 }
 

@@ -29,6 +29,7 @@
 
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -988,9 +989,9 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_conv_z(const PassArgs a) {
 }
 
 // ------------------------------------------------------------ batched form
-// One launch runs one pass of many grids of uneven sizes: a block takes one
-// tile of one (grid, pass) segment, found by binary search over the segments'
-// first tiles.  Every length uses 256 threads per block (T = 4 or 8 threads
+// One launch runs one pass of many grids of uneven sizes (or, cooperatively,
+// all passes): a block takes one tile of one (grid, pass) segment, found by
+// binary search over the segments' first tiles.  Every length uses 256 threads per block (T = 4 or 8 threads
 // per line, 256 / T lines per tile), so one kernel serves all of them; the
 // arithmetic per butterfly is the same as in the single-grid kernels.
 struct BatchItem {
@@ -1000,8 +1001,6 @@ struct BatchItem {
     const void *tw;        // twiddle table of the segment's length
     int code;              // compiled (length, kind), see batch_code
     int from_in;           // 1: the segment reads the `in` buffer (the grid's first pass)
-    int dep;               // persistent launch: index of the grid's previous-pass segment, -1 if none
-    long long dep_total;   // tiles of that segment
 };
 
 struct BatchArgs {
@@ -1011,20 +1010,17 @@ struct BatchArgs {
     void *out;
 };
 
-// Persistent launch over all passes of all grids: work is handed out by an
-// atomic ticket in (pass, grid, tile) order; a segment waits until its grid's
-// previous pass has counted all its tiles done.  A block only ever waits on
-// lower tickets, which blocks that are already running hold, so the launch
-// cannot deadlock whatever the number of resident blocks.
-struct BatchPersistentArgs {
+// One launch over all passes of all grids: the blocks loop over the tiles of
+// pass 0, meet at a grid-wide barrier, loop over the tiles of pass 1, meet
+// again, then pass 2.  The launch is cooperative (every block resident), and
+// every block reaches both barriers, so the barrier cannot wait on a block
+// that is not running.
+struct BatchCoopArgs {
     const BatchItem *items;     // all segments, pass by pass
     int item_begin[4];          // segments of pass p: [item_begin[p], item_begin[p + 1])
-    long long tile_begin[4];    // tickets of pass p: [tile_begin[p], tile_begin[p + 1])
-    unsigned *counters;         // [0]: next ticket; [1 + i]: tiles of segment i done
-    unsigned *status;           // set to 1 if a wait ran past its bound
+    long long tiles[3];         // tiles of pass p, numbered from 0 within the pass
     const void *in;
     void *out;
-    unsigned spin_limit;        // polls before a wait gives up
 };
 
 constexpr int kBatchLengths[8] = {48, 60, 64, 72, 80, 96, 100, 128};
@@ -1106,40 +1102,20 @@ __device__ __forceinline__ int find_segment(const BatchItem *items, int lo, int 
 }
 
 template <class St, bool INV>
-__global__ void __launch_bounds__(256) fft_batch_persistent(const BatchPersistentArgs b) {
+__global__ void __launch_bounds__(256) fft_batch_coop(const BatchCoopArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ long long s_ticket;
-    const long long total = b.tile_begin[3];
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(&b.counters[0], 1u);
-        __syncthreads();
-        const long long ticket = s_ticket;
-        if (ticket >= total) break;  // uniform: every block leaves once the tickets run out
-        const int p = ticket < b.tile_begin[1] ? 0 : (ticket < b.tile_begin[2] ? 1 : 2);
-        const long long pt = ticket - b.tile_begin[p];
-        const int si = find_segment(b.items, b.item_begin[p], b.item_begin[p + 1] - 1, pt);
-        const BatchItem it = b.items[si];
-        if (it.dep >= 0) {
-            if (threadIdx.x == 0) {
-                unsigned polls = 0;
-                while (__hip_atomic_load(&b.counters[1 + it.dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                       (unsigned)it.dep_total) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++polls >= b.spin_limit) {
-                        atomicOr(b.status, 1u);
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll 1
+    for (int p = 0; p < 3; ++p) {
+        for (long long tile = blockIdx.x; tile < b.tiles[p]; tile += gridDim.x) {
+            const int si = find_segment(b.items, b.item_begin[p], b.item_begin[p + 1] - 1, tile);
+            const BatchItem it = b.items[si];
+            batch_dispatch<St, INV>(it, tile - it.tile_begin, b.in, b.out, smem);
+            __syncthreads();  // the next tile reuses the LDS
         }
-        batch_dispatch<St, INV>(it, pt - it.tile_begin, b.in, b.out, smem);
-        // every thread's stores of this tile are ordered before the count
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&b.counters[1 + si], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (p < 2) {
+            __threadfence();  // this pass's stores, before any block reads them
+            cooperative_groups::this_grid().sync();
+        }
     }
 }
 

@@ -125,16 +125,14 @@ bool batch_config(int code, int dtype, BatchConfig *c);
 const void *batch_kernel(int dtype, int inverse);
 size_t batch_item_bytes();
 void batch_item_fill(void *dst, long long offset, long long tile_begin, long long es, long long nlines,
-                     long long nw, long long ntiles, long long total, const void *tw, int code, int from_in,
-                     int dep, long long dep_total);
-const void *batch_persistent_kernel(int dtype, int inverse);
-// Zero the counters, then one persistent launch of `blocks` blocks over every
-// pass of every grid in the table (segments of pass p at
-// [item_begin[p], item_begin[p+1]), tickets [tile_begin[p], tile_begin[p+1])).
-hipError_t launch_batch_persistent(const void *items, const int item_begin[4], const long long tile_begin[4],
-                                   unsigned *counters, unsigned ncounters, unsigned *status, int blocks,
-                                   size_t lds, int dtype, int inverse, const void *in, void *out,
-                                   hipStream_t stream);
+                     long long nw, long long ntiles, long long total, const void *tw, int code, int from_in);
+const void *batch_coop_kernel(int dtype, int inverse);
+// One cooperative launch of `blocks` blocks (all resident) over every pass of
+// every grid in the table: segments of pass p at [item_begin[p],
+// item_begin[p+1]), tiles[p] tiles each, the passes separated by grid-wide
+// barriers.
+hipError_t launch_batch_coop(const void *items, const int item_begin[4], const long long tiles[3], int blocks,
+                             size_t lds, int dtype, int inverse, const void *in, void *out, hipStream_t stream);
 // One launch over `tiles` tiles described by the device array `items`.
 hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t lds, int dtype, int inverse,
                         const void *in, void *out, hipStream_t stream);

@@ -274,9 +274,9 @@ def test_measure_flag_autotunes_and_records_wisdom(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("dtype,direction", [(C64, FWD), (C128, BWD)], ids=["c64-fwd", "c128-bwd"])
 def test_batched_launch_forms_match_single_grid_plans_bitwise(dtype, direction):
-    """The one-launch-per-pass and the persistent batched kernels run the same
-    butterflies as the single-grid kernels: identical bits; the persistent
-    launch reports no wait that gave up."""
+    """The batched launch forms (one launch per pass, and one cooperative
+    launch for every pass) run the same butterflies as the single-grid
+    kernels: identical bits."""
     dims = [(48, 60, 64), (128, 72, 80), (100, 96, 48), (64, 64, 64), (80, 100, 72), (96, 128, 60),
             (8, 1, 3), (45, 27, 2), (1, 64, 1), (60, 1, 100)]
     rng = np.random.Generator(np.random.PCG64(31))
@@ -293,7 +293,7 @@ def test_batched_launch_forms_match_single_grid_plans_bitwise(dtype, direction):
         croft.croft_execute(p, d_in[offs[i]:offs[i + 1]], ref[offs[i]:offs[i + 1]])
         torch.cuda.synchronize()
         croft.croft_plan_destroy(p)
-    for flags in (0,):
+    for flags in (0, croft.CROFT_PERSISTENT):
         plan = croft.croft_plan_create_batched(dims, dtype, direction, flags)
         for rep in range(3):                     # capture, then replays
             out = torch.full_like(d_in, complex(float("nan"), 0))
@@ -301,7 +301,6 @@ def test_batched_launch_forms_match_single_grid_plans_bitwise(dtype, direction):
             torch.cuda.synchronize()
             assert torch.equal(out.view(torch.float64 if dtype == C64 else torch.complex128),
                                ref.view(torch.float64 if dtype == C64 else torch.complex128)), (flags, rep)
-            assert croft.croft_plan_status(plan) == 0
         croft.croft_plan_destroy(plan)
     seen = flat[offs[1]:offs[2]].reshape(80, 72, 128).astype(np.complex128)
     got = ref.cpu().numpy()[offs[1]:offs[2]].reshape(80, 72, 128)
@@ -331,52 +330,19 @@ def test_batched_plan_of_one_grid_runs_it(dims):
     assert torch.equal(out.view(torch.float64), ref.view(torch.float64))
 
 
-PERSISTENT_SKIP = ("the persistent single-launch batched kernel stalled in its first device run; "
-                   "the flag is disabled until the cause is established")
-
-
-@pytest.mark.skip(reason=PERSISTENT_SKIP)
-@pytest.mark.parametrize("dtype,direction", [(C64, FWD), (C128, BWD)], ids=["c64-fwd", "c128-bwd"])
-def test_batched_persistent_launch_matches_single_grid_plans_bitwise(dtype, direction):
-    dims = [(48, 60, 64), (128, 72, 80), (100, 96, 48), (64, 64, 64), (80, 100, 72), (96, 128, 60),
-            (8, 1, 3), (45, 27, 2), (1, 64, 1), (60, 1, 100)]
-    rng = np.random.Generator(np.random.PCG64(31))
-    total = sum(a * b * c for a, b, c in dims)
-    npdt = np.complex64 if dtype == C64 else np.complex128
-    flat = (rng.standard_normal(total) + 1j * rng.standard_normal(total)).astype(npdt)
-    d_in = torch.from_numpy(flat).cuda()
-    ref = torch.empty_like(d_in)
-    plain = croft.croft_plan_create_batched(dims, dtype, direction, 0)
-    croft.croft_execute_batched(plain, d_in, ref)
-    torch.cuda.synchronize()
-    croft.croft_plan_destroy(plain)
-    plan = croft.croft_plan_create_batched(dims, dtype, direction, croft.CROFT_PERSISTENT)
-    for rep in range(3):
-        out = torch.full_like(d_in, complex(float("nan"), 0))
-        croft.croft_execute_batched(plan, d_in, out)
-        torch.cuda.synchronize()
-        assert torch.equal(out, ref)
-        assert croft.croft_plan_status(plan) == 0
-    croft.croft_plan_destroy(plan)
-
-
-def test_persistent_flag_is_refused():
-    with pytest.raises(ValueError, match="disabled"):
-        croft.croft_plan_create_batched([(64, 64, 64)], C64, FWD, croft.CROFT_PERSISTENT)
-
-
 def test_batched_in_place():
     dims = [(64, 48, 60), (72, 80, 96)]
     total = sum(a * b * c for a, b, c in dims)
     rng = np.random.Generator(np.random.PCG64(32))
     flat = (rng.standard_normal(total) + 1j * rng.standard_normal(total)).astype(np.complex64)
     outs = []
-    for flags in (0,):
+    for flags in (0, croft.CROFT_PERSISTENT):
         d = torch.from_numpy(flat).cuda()
         plan = croft.croft_plan_create_batched(dims, C64, FWD, flags)
         croft.croft_execute_batched(plan, d, d)
         torch.cuda.synchronize()
         croft.croft_plan_destroy(plan)
         outs.append(d.cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
     seen = flat[:64 * 48 * 60].reshape(60, 48, 64).astype(np.complex128)
     assert oracle.rel_l2(outs[0][:64 * 48 * 60].reshape(60, 48, 64), oracle.dft3d(seen)) <= TOL[C64]
