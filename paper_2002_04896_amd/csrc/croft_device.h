@@ -505,9 +505,20 @@ __device__ __forceinline__ gchar *uniform_gptr(const void *p, long long byte_off
     return (gchar *)(((unsigned long long)hi << 32) | lo);
 }
 
+// The 32-bit lane offset, re-materialised at each access: left to itself the
+// compiler hoists one 64-bit zero-extended copy out of the tile loop and adds
+// it in 64 bits, so each access would hold a 64-bit address in vector
+// registers instead of a scalar base plus this one offset register.
+__device__ __forceinline__ unsigned lane_reg(unsigned v) {
+    unsigned r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 template <class St, bool NT = false>
 __device__ __forceinline__ typename St::Raw fetch_at(const void *p, long long uniform_elem, unsigned lane_bytes) {
     using Raw = typename St::Raw;
+    lane_bytes = lane_reg(lane_bytes);
     gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(Raw));
     const __attribute__((address_space(1))) Raw *q = (const __attribute__((address_space(1))) Raw *)(b + lane_bytes);
     if constexpr (NT) return __builtin_nontemporal_load(q);
@@ -517,6 +528,7 @@ __device__ __forceinline__ typename St::Raw fetch_at(const void *p, long long un
 template <class St, bool NT = false>
 __device__ __forceinline__ void store_at(void *p, long long uniform_elem, unsigned lane_bytes,
                                          cx<typename St::R> v, int ex) {
+    lane_bytes = lane_reg(lane_bytes);
     gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(typename St::Raw));
     if constexpr (NT) {
         __builtin_nontemporal_store(St::pack(v, ex), (__attribute__((address_space(1))) typename St::Raw *)(b + lane_bytes));
@@ -525,17 +537,28 @@ __device__ __forceinline__ void store_at(void *p, long long uniform_elem, unsign
     }
 }
 
+// The input exponent of every element when a pass is given none.
+static __device__ const int8_t kZeroExponent = 0;
+
 template <class Cfg, class St, int KIND, bool INV>
 __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c, int t, unsigned lane,
                                            long long es, Tile<Cfg, St> &tl) {
     using TL = Tile<Cfg, St>;
     if (!c.valid) return;
-    int ebase = 0;
+    // exponent of element (line q, position j) at ebase(q) + a3 j: the lane
+    // part ebase + a3 t as one 32-bit offset (exponent arrays hold fewer than
+    // 2^31 entries), the rest uniform, as for the data
+    // (no input exponents: every load reads the one zero byte)
+    unsigned elane = 0;
     long long ea3 = 0;
+    const int8_t *ep = &kZeroExponent;
     if constexpr (St::kHalf) {
-        const ExpMap &m = a.em;
-        ebase = (int)((c.q % m.qmod) * m.a0 + (c.q / m.qmod) * m.a1 + c.w * m.a2);
-        ea3 = m.a3;
+        if (a.in_exp) {
+            const ExpMap &m = a.em;
+            ep = a.in_exp;
+            ea3 = m.a3;
+            elane = (unsigned)((c.q % m.qmod) * m.a0 + (c.q / m.qmod) * m.a1 + c.w * m.a2 + ea3 * t);
+        }
     }
 #pragma unroll
     for (int b = 0; b < TL::B0; ++b) {
@@ -546,7 +569,10 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
                 const long long u = c.tbase + (long long)(b * Cfg::T + q * TL::NB0) * es;
                 const typename St::Raw r = fetch_at<St, Cfg::kNT>(a.in, u, lane);
                 int ex = 0;
-                if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + ea3 * (j + q * TL::NB0)] : 0;
+                if constexpr (St::kHalf) {
+                    gchar *eb = uniform_gptr(ep, ea3 * (b * Cfg::T + q * TL::NB0));
+                    ex = *(const __attribute__((address_space(1))) int8_t *)(eb + lane_reg(elane));
+                }
                 if constexpr (TL::kRaw) {
                     tl.e[b][q] = r;
                     if constexpr (St::kHalf) tl.ex[b][q] = ex;
@@ -557,6 +583,20 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
         }
     }
 }
+
+template <typename R>
+__device__ __forceinline__ R uniform_r(R v) {
+    if constexpr (sizeof(R) == 4) {
+        return __builtin_bit_cast(R, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+        const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+        return __builtin_bit_cast(R, ((unsigned long long)hi << 32) | lo);
+    }
+}
+template <typename R>
+__device__ __forceinline__ cx<R> uniform_cx(cx<R> v) { return {uniform_r(v.x), uniform_r(v.y)}; }
 
 // IO bit 0: the first stage reads its inputs from LDS (natural order)
 // instead of the tile; bit 1: the last stage writes its outputs to LDS
@@ -603,7 +643,13 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
             if constexpr (Ns > 1) {
                 const int k = j % Ns;
 #pragma unroll
-                for (int q = 1; q < RAD; ++q) v[b][q] = cmul(v[b][q], tws[kTw + (q - 1) * Ns + k]);
+                for (int q = 1; q < RAD; ++q) {
+                    cx<R> w = tws[kTw + (q - 1) * Ns + k];
+                    // a wavefront of one tile position: the twiddle is the
+                    // same in every lane and lives in scalar registers
+                    if constexpr (KIND != kContiguous && L % 64 == 0) w = uniform_cx(w);
+                    v[b][q] = cmul(v[b][q], w);
+                }
             }
             Dft<RAD, R>::run(v[b]);
         }
@@ -701,7 +747,9 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
     unsigned *red = reinterpret_cast<unsigned *>(smem + Cfg::kLdsData + (size_t)Cfg::kTwN * sizeof(cx<R>));
     const int tid = threadIdx.x;
     const int l = KIND == kContiguous ? tid / T : tid % L;
-    const int t = KIND == kContiguous ? tid % T : tid / L;
+    // with whole wavefronts of lines, t is the wavefront's index: uniform
+    const int t = KIND == kContiguous ? tid % T
+                  : (L % 64 == 0 ? (int)__builtin_amdgcn_readfirstlane((unsigned)(tid / L)) : tid / L);
 
     if constexpr (Cfg::kTwN > 0) {
         const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
@@ -1041,7 +1089,9 @@ __device__ __forceinline__ void batch_tile(const PassArgs &a, long long tile, un
     unsigned *red = nullptr;
     const int tid = threadIdx.x;
     const int l = KIND == kContiguous ? tid / T : tid % L;
-    const int t = KIND == kContiguous ? tid % T : tid / L;
+    // with whole wavefronts of lines, t is the wavefront's index: uniform
+    const int t = KIND == kContiguous ? tid % T
+                  : (L % 64 == 0 ? (int)__builtin_amdgcn_readfirstlane((unsigned)(tid / L)) : tid / L);
     if constexpr (Cfg::kTwN > 0) {
         const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
         for (int i = tid; i < Cfg::kTwN; i += Cfg::kBlock) tws[i] = W[tw_source<Cfg>(i)];

@@ -212,7 +212,7 @@ def test_execute_argument_errors_on_device():
 
 
 @pytest.mark.parametrize("dtype", [C64, F16], ids=["c64", "f16"])
-@pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20)], ids=str)
+@pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20), (4, 512, 80)], ids=str)
 def test_every_compiled_candidate_gives_identical_bits(dtype, shape, tmp_path, monkeypatch):
     """Every autotuner candidate (and persistent-grid size) runs the same
     arithmetic in the same order, so the outputs agree bit for bit; the
@@ -247,7 +247,7 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, tmp_path, m
     lengths = {(p["n"], p["kind"]) for p in info["passes"]}
     tried = 0
     for n, kind in lengths:
-        for cand in range(5):
+        for cand in range(8):
             for waves in (0, 1, 3):
                 wisdom.write_text(f"{n} {kind} {dtype} {cand} {waves}\n")
                 got, got_e, ginfo = run()
@@ -257,7 +257,7 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, tmp_path, m
                     (n, kind, cand, waves)
                 assert torch.equal(got_e, ref_e)
                 tried += 1
-    assert tried >= 24
+    assert tried >= 48
 
 
 def test_measure_flag_autotunes_and_records_wisdom(tmp_path, monkeypatch):
