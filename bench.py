@@ -12,8 +12,10 @@ each pass launch on the stream the pass runs on, over the timed region.
 `--calibrate-copy` instead times a plain device copy of the same bytes (used
 to scale the HBM byte counters).  The line also carries the half-storage
 (FP16, BF16 at 512^3) and batched (64 uneven grids) forms, each timed next to
-the plain complex64 form on the same GPU with its error against it
-(`--no-forms` skips them).
+the plain complex64 form on the same GPU with its error against it, and the
+smaller cubes (32^3 latency; 256^3 and 384^3 forward and inverse, warm and
+with the Infinity Cache flushed) under "configs" (`--no-forms` skips both).
+The effective rate is also given as a fraction of a measured device copy.
 """
 from __future__ import annotations
 
@@ -239,6 +241,102 @@ def measure_large(torch, np, croft, pme, steps):
             "dc_minus_total_charge": dc.real - qtot}
 
 
+def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
+    """GB/s of a plain device-to-device copy of nbytes (read + write counted)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / ms / 1e6
+
+
+def measure_configs(torch, np, croft, synth):
+    """The smaller cubes: 32^3 (U[-1,1), latency-bound: median of 200
+    individually timed calls, and the round trip), and 256^3 and 384^3
+    (N(0,1)) forward and inverse, warm (back to back) and with the 256 MB
+    Infinity Cache flushed before each call by writing a 512 MiB buffer."""
+    out = {}
+    a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def one(fn, flush=None):
+        if flush is not None:
+            flush.fill_(0.0)
+        a_.record()
+        fn()
+        b_.record()
+        torch.cuda.synchronize()
+        return a_.elapsed_time(b_)
+
+    # 32^3
+    n = 32
+    x = torch.from_numpy(synth.uniform_c((n, n, n), seed=1).astype(np.complex64)).cuda()
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    f = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+    bk = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_BACKWARD)
+    for _ in range(20):
+        croft.croft_execute(f, x, y)
+    t_f = [one(lambda: croft.croft_execute(f, x, y)) for _ in range(200)]
+    t_b = [one(lambda: croft.croft_execute(bk, y, z)) for _ in range(200)]
+    croft.croft_plan_destroy(f)
+    croft.croft_plan_destroy(bk)
+    # the same transform as one cooperative launch (a batched plan of one grid)
+    c = croft.croft_plan_create_batched([(n, n, n)], croft.CROFT_C64, croft.CROFT_FORWARD, croft.CROFT_PERSISTENT)
+    yc = torch.empty_like(x)
+    for _ in range(20):
+        croft.croft_execute_batched(c, x, yc)
+    t_c = [one(lambda: croft.croft_execute_batched(c, x, yc)) for _ in range(200)]
+    croft.croft_plan_destroy(c)
+    out["c64_32cube"] = {"forward_median_us": 1e3 * float(np.median(t_f)),
+                         "inverse_median_us": 1e3 * float(np.median(t_b)),
+                         "forward_one_launch_median_us": 1e3 * float(np.median(t_c)),
+                         "one_launch_bitwise_equal": bool(torch.equal(yc, y)),
+                         "round_trip_rel_l2": rel_l2_dev(torch, z / n ** 3, x)}
+    flush = torch.empty(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
+    for n in (256, 384):
+        x = torch.from_numpy(synth.normal_c((n, n, n), seed=2).astype(np.complex64)).cuda()
+        y = torch.empty_like(x)
+        z = torch.empty_like(x)
+        f = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+        bk = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_BACKWARD)
+        info = croft.croft_plan_info(f)
+        r = {}
+        for name, fn in (("forward", lambda: croft.croft_execute(f, x, y)),
+                         ("inverse", lambda: croft.croft_execute(bk, y, z))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            a_.record()
+            for _ in range(50):
+                fn()
+            b_.record()
+            torch.cuda.synchronize()
+            warm = a_.elapsed_time(b_) / 50
+            flushed = float(np.median([one(fn, flush) for _ in range(20)]))
+            r[name + "_warm_ms"] = warm
+            r[name + "_flushed_ms"] = flushed
+        r["GFLOPs_warm"] = flops_5nlogn(n ** 3) / r["forward_warm_ms"] / 1e6
+        r["effective_GBps_flushed"] = info["algorithmic_bytes"] / r["forward_flushed_ms"] / 1e6
+        r["round_trip_rel_l2"] = rel_l2_dev(torch, z / n ** 3, x)
+        croft.croft_plan_destroy(f)
+        croft.croft_plan_destroy(bk)
+        out[f"c64_{n}cube"] = r
+        del x, y, z
+    del flush
+    torch.cuda.empty_cache()
+    return out
+
+
 def measure_forms(torch, np, croft, synth, steps):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
@@ -375,6 +473,7 @@ def main():
     # sanity: DC bin equals the total charge
     dc = d_out[0, 0, 0].item()
     croft.croft_plan_destroy(plan)
+    copy_gbps = copy_bandwidth(torch)
 
     gflops = flops_5nlogn(N) / ms / 1e6
     alg_bytes = info["algorithmic_bytes"]
@@ -397,6 +496,8 @@ def main():
                    "nx": n, "ny": n, "nz": n, "slabs": args.slabs, "parallelism": "single GPU"},
         "effective_hbm_GBps": alg_bytes / ms / 1e6,
         "effective_frac_of_8TBps": alg_bytes / ms / 1e6 / HBM_PEAK_GBPS,
+        "copy_GBps": copy_gbps,
+        "effective_frac_of_copy": alg_bytes / ms / 1e6 / copy_gbps,
         "pass_ms": pass_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
@@ -413,6 +514,7 @@ def main():
         line["forms"]["convolution"] = measure_conv(torch, np, croft, synth, x, max(10, args.steps // 2))
         line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5))
         line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2)))
+        line["configs"] = measure_configs(torch, np, croft, synth)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, n)
     print(json.dumps(line))

@@ -304,6 +304,24 @@ __device__ __forceinline__ int line_exponent(float mx) {
     return e < -128 ? -128 : (e > 127 ? 127 : e);
 }
 
+// Largest of v over each aligned group of T lanes (T a power of two up to 64)
+// by a butterfly of cross-lane moves: DPP quad permutations for lane
+// distances 1 and 2, ds_swizzle for 4, 8 and 16 (within 32-lane halves),
+// ds_bpermute for 32.  Unsigned order, as for the bits of non-negative floats.
+template <int T>
+__device__ __forceinline__ unsigned lanes_max_u32(unsigned v) {
+    if constexpr (T >= 2) v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));
+    if constexpr (T >= 4) v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));
+    if constexpr (T >= 8) v = max(v, (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x101F));
+    if constexpr (T >= 16) v = max(v, (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x201F));
+    if constexpr (T >= 32) v = max(v, (unsigned)__builtin_amdgcn_ds_swizzle((int)v, 0x401F));
+    if constexpr (T >= 64) {
+        const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+        v = max(v, (unsigned)__builtin_amdgcn_ds_bpermute((lane ^ 32) << 2, (int)v));
+    }
+    return v;
+}
+
 // The inverse transform is swap(DFT(swap(x))) with swap(a + ib) = b + ia.
 template <bool INV, typename R>
 __device__ __forceinline__ cx<R> maybe_swap(cx<R> v) {
@@ -683,9 +701,14 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
                     for (int q = 0; q < RAD; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[b][q].x), fabsf(v[b][q].y)));
                 }
             }
-            atomicMax(&red[l], __float_as_uint(mx));
-            stage_sync<Cfg::kWaveSync>();
-            ex = line_exponent(__uint_as_float(red[l]));
+            if constexpr (Cfg::kWaveSync) {
+                // the line's T lanes are one aligned group of its wavefront
+                ex = line_exponent(__uint_as_float(lanes_max_u32<T>(__float_as_uint(mx))));
+            } else {
+                atomicMax(&red[l], __float_as_uint(mx));
+                stage_sync<Cfg::kWaveSync>();
+                ex = line_exponent(__uint_as_float(red[l]));
+            }
             ex_out = ex;
         }
         if (c.valid) {
@@ -793,7 +816,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
         }
 
         int ex = 0;
-        if constexpr (St::kHalf) {
+        if constexpr (St::kHalf && !Cfg::kWaveSync) {
             if (t == 0) red[l] = 0u;
             stage_sync<Cfg::kWaveSync>();
         }
@@ -812,6 +835,190 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
         tile = nt;
         tx = ntx;
         w = nw;
+    }
+}
+
+// ------------------------------------------------- lane-per-line strided pass
+// A strided pass of length 512 = 8 x 8 x 8 with one line per lane: a tile is
+// 64 neighbouring lines (each tile position a 64-element row segment, 256
+// bytes at 4-byte storage), and wavefront s (of 8) holds positions s + 8m,
+// m < 64, of every line of the tile.  It runs the three radix-8 Stockham
+// stages of the other kernels butterfly for butterfly, with the same twiddles
+// and the same operations, so its results are bit-identical to theirs; but
+// the first two stages stay in the wavefront's registers.  Stage-0 butterflies
+// j = s + 8q (q < 8) read positions s + 8(q + 8p), p < 8, which are all the
+// wavefront's own, and write outputs 8j + p = 64q + 8s + p; stage-1 butterfly
+// 8s + r reads outputs 8s + r + 64q of stage 0, i.e. output r of butterfly
+// s + 8q: the same wavefront again.  Stage-1 butterfly 8s + r writes
+// 64s + r + 8p; stage 2 (butterflies 8s + u, u < 8, reading j + 64q) needs
+// one element from every wavefront, so there is one exchange through LDS,
+// made as real parts then imaginary parts through a 128 KiB area.  Every
+// position, every twiddle index and the tile origin are uniform in a
+// wavefront: addresses are a scalar base plus the lane's 4- or 8-byte offset,
+// and twiddles are read from LDS into scalar registers.
+constexpr int kLanesN = 512, kLanesL = 64, kLanesBlock = 512;
+template <class St>
+struct LanesLds {
+    using R = typename St::R;
+    static constexpr size_t kX = (size_t)kLanesN * kLanesL * sizeof(R);   // one component of the tile
+    static constexpr size_t kTw = kX;                                      // w_512^m, m < 512
+    static constexpr size_t kRed = kTw + (size_t)kLanesN * sizeof(cx<R>);  // [8][64] line maxima
+    static constexpr size_t kBytes = kRed + 8 * kLanesL * sizeof(unsigned);
+};
+
+template <class St, bool INV, bool NT>
+__global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
+    using R = typename St::R;
+    using Lay = LanesLds<St>;
+    static_assert(sizeof(R) == 4, "FP32 compute: 64 elements per lane in registers");
+    constexpr int N = kLanesN, L = kLanesL;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R *xl = reinterpret_cast<R *>(smem);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Lay::kTw);
+    unsigned *red = reinterpret_cast<unsigned *>(smem + Lay::kRed);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int s = (int)__builtin_amdgcn_readfirstlane((unsigned)(tid >> 6));
+    {
+        const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
+        for (int i = tid; i < N; i += kLanesBlock) tws[i] = W[i];
+        __syncthreads();
+    }
+    long long tile = blockIdx.x;
+    if (tile >= a.total) return;
+    const long long G = gridDim.x;
+    const long long es = a.es;
+    long long tx = tile % a.ntiles, w = tile / a.ntiles;
+    const long long gx = G % a.ntiles, gw = G / a.ntiles;
+    const unsigned lane_b = (unsigned)lane * (unsigned)sizeof(typename St::Raw);
+    for (;;) {
+        const long long q = tx * L + lane;  // this lane's line
+        const bool valid = q < es;
+        const long long tbase = tx * L + w * es * N;
+        cx<R> v[64];
+        if (valid) {
+            unsigned elane = 0;
+            long long ea3 = 0;
+            const int8_t *ep = &kZeroExponent;
+            if constexpr (St::kHalf) {
+                if (a.in_exp) {
+                    const ExpMap &m = a.em;
+                    ep = a.in_exp;
+                    ea3 = m.a3;
+                    elane = (unsigned)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2);
+                }
+            }
+            // every load in flight before the first decode
+            typename St::Raw raw[64];
+            int ex[St::kHalf ? 64 : 1];
+#pragma unroll
+            for (int m = 0; m < 64; ++m) {
+                const long long pos = s + 8 * m;
+                raw[m] = fetch_at<St, NT>(a.in, tbase + pos * es, lane_b);
+                if constexpr (St::kHalf) {
+                    gchar *eb = uniform_gptr(ep, ea3 * pos);
+                    ex[m] = *(const __attribute__((address_space(1))) int8_t *)(eb + lane_reg(elane));
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < 64; ++m) v[m] = maybe_swap<INV>(St::decode(raw[m], St::kHalf ? ex[m] : 0));
+        } else {
+#pragma unroll
+            for (int m = 0; m < 64; ++m) v[m] = {R(0), R(0)};
+        }
+        // stage 0: butterfly s + 8q on v[q + 8p]; output p to v[q + 8p]
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+            cx<R> t[8];
+#pragma unroll
+            for (int p = 0; p < 8; ++p) t[p] = v[qq + 8 * p];
+            Dft<8, R>::run(t);
+#pragma unroll
+            for (int p = 0; p < 8; ++p) v[qq + 8 * p] = t[p];
+        }
+        // stage 1: butterfly 8s + r on v[8r + p] (output r of stage-0
+        // butterfly s + 8p), twiddles w_64^(p r) = w_512^(8 p r)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            cx<R> t[8];
+            t[0] = v[8 * r];
+#pragma unroll
+            for (int p = 1; p < 8; ++p) t[p] = cmul(v[8 * r + p], uniform_cx(tws[8 * p * r]));
+            Dft<8, R>::run(t);
+#pragma unroll
+            for (int p = 0; p < 8; ++p) v[8 * r + p] = t[p];
+        }
+        // exchange: v[8r + p] is element 64s + r + 8p; stage-2 butterfly
+        // 8s + u reads elements 8s + u + 64p into y[8u + p]
+        cx<R> y[64];
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+            __syncthreads();  // the previous readers of the area are done
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+#pragma unroll
+                for (int p = 0; p < 8; ++p)
+                    xl[(64 * s + r + 8 * p) * L + lane] = part ? v[8 * r + p].y : v[8 * r + p].x;
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const R e = xl[(8 * s + u + 64 * p) * L + lane];
+                    if (part) y[8 * u + p].y = e;
+                    else y[8 * u + p].x = e;
+                }
+        }
+        // stage 2: butterfly j = 8s + u, twiddles w_512^(p j); outputs j + 64p
+        float mx = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = 8 * s + u;
+            cx<R> t[8];
+            t[0] = y[8 * u];
+#pragma unroll
+            for (int p = 1; p < 8; ++p) t[p] = cmul(y[8 * u + p], uniform_cx(tws[p * j]));
+            Dft<8, R>::run(t);
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+                y[8 * u + p] = t[p];
+                if constexpr (St::kHalf) mx = fmaxf(mx, fmaxf(fabsf(t[p].x), fabsf(t[p].y)));
+            }
+        }
+        int ex = 0;
+        if constexpr (St::kHalf) {
+            // the line's maximum over the eight wavefronts
+            red[s * L + lane] = __float_as_uint(mx);
+            __syncthreads();
+            unsigned mb = red[lane];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) mb = max(mb, red[k * L + lane]);
+            ex = line_exponent(__uint_as_float(mb));
+        }
+        if (valid) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int p = 0; p < 8; ++p) {
+                    const long long pos = 8 * s + u + 64 * p;
+                    store_at<St, NT>(a.out, tbase + pos * es, lane_b, maybe_swap<INV>(y[8 * u + p]), ex);
+                }
+            if constexpr (St::kHalf) {
+                if (s == 0 && a.out_exp) {
+                    const ExpMap &m = a.em;
+                    a.out_exp[(q % m.qmod) * m.b0 + (q / m.qmod) * m.b1 + w * m.b2] = (int8_t)ex;
+                }
+            }
+        }
+        tile += G;
+        if (tile >= a.total) break;
+        tx += gx;
+        w += gw;
+        if (tx >= a.ntiles) {
+            tx -= a.ntiles;
+            w += 1;
+        }
     }
 }
 
@@ -1205,6 +1412,25 @@ Entry make_entry(int cand) {
     e.block = Cfg::kBlock;
     e.lds = Cfg::kLds;
     e.plan = Cfg::plan;
+    return e;
+}
+
+// The lane-per-line strided configuration of length 512 (4- or 8-byte storage).
+template <class St, int DT, bool NT>
+Entry make_lanes_entry(int cand) {
+    static_assert(LanesLds<St>::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    Entry e;
+    e.n = kLanesN;
+    e.kind = kStrided;
+    e.dtype = DT;
+    e.cand = cand;
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes512<St, false, NT>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes512<St, true, NT>);
+    e.T = kLanesBlock / kLanesL;
+    e.L = kLanesL;
+    e.block = kLanesBlock;
+    e.lds = LanesLds<St>::kBytes;
+    e.plan = make_rplan(kLanesN);
     return e;
 }
 
