@@ -278,7 +278,7 @@ def test_batched_launch_forms_match_single_grid_plans_bitwise(dtype, direction):
     launch for every pass) run the same butterflies as the single-grid
     kernels: identical bits."""
     dims = [(48, 60, 64), (128, 72, 80), (100, 96, 48), (64, 64, 64), (80, 100, 72), (96, 128, 60),
-            (8, 1, 3), (45, 27, 2), (1, 64, 1), (60, 1, 100)]
+            (8, 1, 3), (45, 27, 2), (1, 64, 1), (60, 1, 100), (128, 128, 48), (96, 72, 1)]
     rng = np.random.Generator(np.random.PCG64(31))
     total = sum(a * b * c for a, b, c in dims)
     npdt = np.complex64 if dtype == C64 else np.complex128
