@@ -151,7 +151,7 @@ int build_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<P
             p.nw = N / (p.es * n);
         }
         int cand = 0, waves = 1;
-        wisdom_lookup(n, p.kind, dtype, dir, &cand, &waves);
+        wisdom_lookup(n, p.kind, dtype, dir, wisdom_axis(p.kind, axis), &cand, &waves);
         if (!select_kernel(n, p.kind, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
             return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, p.kind, dtype, true, 0, &p.cfg))
@@ -212,7 +212,7 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
     xp.es = 1;
     xp.nlines = (long long)g.ny * g.nz;
     int cand = 0, waves = 1;
-    wisdom_lookup(m, kRealX, dtype, tune_dir, &cand, &waves);
+    wisdom_lookup(m, kRealX, dtype, tune_dir, -1, &cand, &waves);
     if (!select_kernel(m, kRealX, dtype, false, cand, &xp.cfg))
         return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no real x kernel for nx = %d (half length %d)", g.nx, m);
     xp.cfg.grid_waves = waves;
@@ -227,7 +227,7 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
         p.es = axis == 1 ? h : h * g.ny;
         p.nlines = p.es;
         p.nw = axis == 1 ? g.nz : 1;
-        wisdom_lookup(n, kStrided, dtype, tune_dir, &cand, &waves);
+        wisdom_lookup(n, kStrided, dtype, tune_dir, axis, &cand, &waves);
         if (!select_kernel(n, kStrided, dtype, (flags & CROFT_FORCE_GENERIC) != 0, cand, &p.cfg))
             return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, kStrided, dtype, true, 0, &p.cfg))
@@ -259,7 +259,7 @@ int build_conv_passes(const Geometry &g, int dtype, int flags, std::vector<PassL
     c.kind = kConvZ;
     c.hx = (long long)g.nx / 2 + 1;
     int cand = 0, waves = 1;
-    wisdom_lookup(c.n, kConvZ, dtype, 0, &cand, &waves);
+    wisdom_lookup(c.n, kConvZ, dtype, 0, -1, &cand, &waves);
     const bool compiled = select_kernel(c.n, kConvZ, dtype, false, cand, &c.cfg);
     if ((!compiled || !lane_offset_fits(c, dtype)) && !select_generic_conv(c.n, dtype, &c.cfg))
         return fail(CROFT_ERR_UNSUPPORTED_SIZE,
@@ -540,19 +540,23 @@ int measure_passes(croft_plan *p) {
     }
     const bool persist = !(p->flags & CROFT_NO_WISDOM);
     const bool inv = p->dir == CROFT_BACKWARD;
-    std::map<std::tuple<int, int>, KernelConfig> best;  // (n, kind) -> configuration
+    // (n, kind, wisdom axis) -> configuration: strided passes are tuned per
+    // axis, as their strides differ
+    std::map<std::tuple<int, int, int>, KernelConfig> best;
     for (auto &ps : p->passes) {
         for (PassLaunch &pl : ps) {
-            if (pl.cfg.generic || best.count({pl.n, pl.kind})) continue;
+            const int wax = wisdom_axis(pl.kind, pl.axis);
+            if (pl.cfg.generic || best.count({pl.n, pl.kind, wax})) continue;
             const int ncand = kernel_candidates(pl.n, pl.kind, p->dtype);
             float best_ms = 1e30f;
             KernelConfig pick = pl.cfg;
-            // every pass of the plan with this (length, kind): a choice is
-            // timed on all the geometries it will run (e.g. both y and z)
+            // every pass of the plan with this (length, kind, axis): a choice
+            // is timed on all the geometries it will run (e.g. the z passes of
+            // every grid of a batched plan)
             std::vector<const PassLaunch *> same;
             for (auto &ps2 : p->passes)
                 for (const PassLaunch &q : ps2)
-                    if (q.n == pl.n && q.kind == pl.kind) same.push_back(&q);
+                    if (q.n == pl.n && q.kind == pl.kind && wisdom_axis(q.kind, q.axis) == wax) same.push_back(&q);
             for (int c = 0; c < ncand && rc == CROFT_SUCCESS; ++c) {
                 KernelConfig cfg;
                 if (!select_kernel(pl.n, pl.kind, p->dtype, false, c, &cfg) || cfg.candidate != c) continue;
@@ -603,15 +607,15 @@ int measure_passes(croft_plan *p) {
                 }
             }
             if (rc != CROFT_SUCCESS) break;
-            best[{pl.n, pl.kind}] = pick;
-            wisdom_record(pl.n, pl.kind, p->dtype, pick.candidate, pick.grid_waves, persist);
+            best[{pl.n, pl.kind, wax}] = pick;
+            wisdom_record(pl.n, pl.kind, p->dtype, wax, pick.candidate, pick.grid_waves, persist);
         }
     }
     cleanup();
     if (rc != CROFT_SUCCESS) return rc;
     for (auto &ps : p->passes)
         for (PassLaunch &pl : ps) {
-            auto it = best.find({pl.n, pl.kind});
+            auto it = best.find({pl.n, pl.kind, wisdom_axis(pl.kind, pl.axis)});
             if (it != best.end()) pl.cfg = it->second;
         }
     return CROFT_SUCCESS;

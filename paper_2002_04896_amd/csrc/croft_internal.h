@@ -139,9 +139,13 @@ hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t l
 
 // ---- wisdom (croft_tune.cpp) ----
 // dir: -1 forward, +1 backward, 0 a pass that runs in both directions (the
-// forward-only built-in choices apply to -1 only).
-bool wisdom_lookup(int n, int kind, int dtype, int dir, int *cand, int *waves);
-void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist);
+// forward-only built-in choices apply to -1 only).  axis: the grid axis of a
+// strided pass (a choice for that axis first, then one for any axis), -1
+// for the other kinds.
+bool wisdom_lookup(int n, int kind, int dtype, int dir, int axis, int *cand, int *waves);
+void wisdom_record(int n, int kind, int dtype, int axis, int cand, int waves, bool persist);
+// The axis a pass's wisdom is keyed on.
+inline int wisdom_axis(int kind, int axis) { return kind == kStrided ? axis : -1; }
 
 // ---- planner (croft_plan.cpp) ----
 bool smooth_length(int n);

@@ -5,12 +5,16 @@
 // size (in resident-block waves; 0 = one block per tile).  Choices measured in
 // this process are kept in memory; when the environment variable CROFT_WISDOM
 // names a file, plans also read it and CROFT_MEASURE plans append to it.
-// File format, one choice per line:  n kind dtype candidate waves
-// Lookup order: the CROFT_WISDOM file, choices measured in this process, for
-// forward plans the forward-only built-in choices, the built-in table below (measured on an MI355X with CROFT_MEASURE on cubic
-// grids; kinds 2 and 3, the real x pass and the fused multiply pass, on real
-// and convolution plans of cubic grids), then candidate 0 with one resident
-// wave.
+// File format, one choice per line:  n kind dtype candidate waves [axis]
+// A strided pass also has a choice of its own per grid axis (1 = y, 2 = z:
+// their strides differ, and so can their best tiles); a line without an axis
+// serves every axis.  Lookup order: the CROFT_WISDOM file, choices measured
+// in this process, for forward plans the forward-only built-in choices, the
+// per-axis built-in choices, the built-in table below (measured on an MI355X
+// with CROFT_MEASURE on cubic grids; kinds 2 and 3, the real x pass and the
+// fused multiply pass, on real and convolution plans of cubic grids), then
+// candidate 0 with one resident wave.  At each step an entry for the pass's
+// axis comes before one for any axis.
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -64,18 +68,31 @@ const Builtin kBuiltinForward[] = {
     {512, 1, 0, 2, 1},
 };
 
-std::mutex g_mu;
-std::map<std::tuple<int, int, int>, std::pair<int, int>> g_mem;
+// Per-axis choices (n kind dtype axis candidate waves): 512 strided with
+// 16-bit storage, where the y pass (2 KiB stride) is fastest with the
+// 32-line tiles and the z pass (1 MiB stride) with one line per lane.
+struct BuiltinAxis {
+    int n, kind, dtype, axis, cand, waves;
+};
+const BuiltinAxis kBuiltinAxis[] = {
+    {512, 1, 2, 1, 5, 2}, {512, 1, 2, 2, 6, 1}, {512, 1, 3, 1, 5, 2}, {512, 1, 3, 2, 6, 1},
+};
 
-bool read_file(const char *path, int n, int kind, int dtype, int *cand, int *waves) {
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_mem;  // (n, kind, dtype, axis or -1)
+
+// The last matching line for this axis (axis >= 0) or for any axis (axis -1).
+bool read_file(const char *path, int n, int kind, int dtype, int axis, int *cand, int *waves) {
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
     bool found = false;
-    int a, b, c, d, e;
+    int a, b, c, d, e, x;
     char line[256];
     while (std::fgets(line, sizeof line, f)) {
-        if (std::sscanf(line, "%d %d %d %d %d", &a, &b, &c, &d, &e) == 5 && a == n && b == kind && c == dtype) {
-            *cand = d;  // the last matching line wins
+        const int got = std::sscanf(line, "%d %d %d %d %d %d", &a, &b, &c, &d, &e, &x);
+        if (got < 5 || a != n || b != kind || c != dtype) continue;
+        if ((axis < 0 && got == 5) || (axis >= 0 && got == 6 && x == axis)) {
+            *cand = d;
             *waves = e;
             found = true;
         }
@@ -85,19 +102,34 @@ bool read_file(const char *path, int n, int kind, int dtype, int *cand, int *wav
 }
 }  // namespace
 
-bool wisdom_lookup(int n, int kind, int dtype, int dir, int *cand, int *waves) {
+bool wisdom_lookup(int n, int kind, int dtype, int dir, int axis, int *cand, int *waves) {
     std::lock_guard<std::mutex> lk(g_mu);
     const char *path = std::getenv("CROFT_WISDOM");
-    if (path && *path && read_file(path, n, kind, dtype, cand, waves)) return true;
-    auto it = g_mem.find({n, kind, dtype});
-    if (it != g_mem.end()) {
-        *cand = it->second.first;
-        *waves = it->second.second;
-        return true;
+    if (path && *path) {
+        if (axis >= 0 && read_file(path, n, kind, dtype, axis, cand, waves)) return true;
+        if (read_file(path, n, kind, dtype, -1, cand, waves)) return true;
+    }
+    const int axes[2] = {axis, -1};
+    for (int i = axis >= 0 ? 0 : 1; i < 2; ++i) {
+        auto it = g_mem.find({n, kind, dtype, axes[i]});
+        if (it != g_mem.end()) {
+            *cand = it->second.first;
+            *waves = it->second.second;
+            return true;
+        }
     }
     if (dir == -1) {
         for (const Builtin &b : kBuiltinForward) {
             if (b.n == n && b.kind == kind && b.dtype == dtype) {
+                *cand = b.cand;
+                *waves = b.waves;
+                return true;
+            }
+        }
+    }
+    if (axis >= 0) {
+        for (const BuiltinAxis &b : kBuiltinAxis) {
+            if (b.n == n && b.kind == kind && b.dtype == dtype && b.axis == axis) {
                 *cand = b.cand;
                 *waves = b.waves;
                 return true;
@@ -114,13 +146,14 @@ bool wisdom_lookup(int n, int kind, int dtype, int dir, int *cand, int *waves) {
     return false;
 }
 
-void wisdom_record(int n, int kind, int dtype, int cand, int waves, bool persist) {
+void wisdom_record(int n, int kind, int dtype, int axis, int cand, int waves, bool persist) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_mem[{n, kind, dtype}] = {cand, waves};
+    g_mem[{n, kind, dtype, axis}] = {cand, waves};
     const char *path = std::getenv("CROFT_WISDOM");
     if (!persist || !path || !*path) return;
     if (FILE *f = std::fopen(path, "a")) {
-        std::fprintf(f, "%d %d %d %d %d\n", n, kind, dtype, cand, waves);
+        if (axis >= 0) std::fprintf(f, "%d %d %d %d %d %d\n", n, kind, dtype, cand, waves, axis);
+        else std::fprintf(f, "%d %d %d %d %d\n", n, kind, dtype, cand, waves);
         std::fclose(f);
     }
 }

@@ -171,6 +171,21 @@ def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
     assert passes[2]["candidate"] == "4" and passes[2]["block"] == "512"
 
 
+def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
+    # 16-bit storage at 512: the built-in choices differ between the y pass
+    # (32-line tiles) and the z pass (one line per lane)
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C16F)
+    assert [p["candidate"] for p in passes][1:] == ["5", "6"]
+    assert passes[2]["L"] == "64" and passes[2]["T"] == "8"
+    # a file line for any axis comes before the built-in per-axis choices ...
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 2 4 1\n", 512, 512, 512, croft.CROFT_C16F)
+    assert [p["candidate"] for p in passes][1:] == ["4", "4"]
+    # ... and a line for the pass's own axis before one for any axis
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 2 4 1\n512 1 2 2 2 2\n", 512, 512, 512,
+                                   croft.CROFT_C16F)
+    assert [p["candidate"] for p in passes][1:] == ["4", "2"] and passes[2]["waves"] == "2"
+
+
 def test_wisdom_unknown_candidate_falls_back_to_default(tmp_path, monkeypatch):
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 9 1\n", 512, 512, 512)
     assert passes[1]["candidate"] == "0"
