@@ -839,46 +839,58 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
 }
 
 // ------------------------------------------------- lane-per-line strided pass
-// A strided pass of length 512 = 8 x 8 x 8 with one line per lane: a tile is
-// 64 neighbouring lines (each tile position a 64-element row segment, 256
-// bytes at 4-byte storage), and wavefront s (of 8) holds positions s + 8m,
-// m < 64, of every line of the tile.  It runs the three radix-8 Stockham
-// stages of the other kernels butterfly for butterfly, with the same twiddles
-// and the same operations, so its results are bit-identical to theirs; but
-// the first two stages stay in the wavefront's registers.  Stage-0 butterflies
-// j = s + 8q (q < 8) read positions s + 8(q + 8p), p < 8, which are all the
-// wavefront's own, and write outputs 8j + p = 64q + 8s + p; stage-1 butterfly
-// 8s + r reads outputs 8s + r + 64q of stage 0, i.e. output r of butterfly
-// s + 8q: the same wavefront again.  Stage-1 butterfly 8s + r writes
-// 64s + r + 8p; stage 2 (butterflies 8s + u, u < 8, reading j + 64q) needs
-// one element from every wavefront, so there is one exchange through LDS,
-// made as real parts then imaginary parts through a 128 KiB area.  Every
-// position, every twiddle index and the tile origin are uniform in a
-// wavefront: addresses are a scalar base plus the lane's 4- or 8-byte offset,
-// and twiddles are read from LDS into scalar registers.
-constexpr int kLanesN = 512, kLanesL = 64, kLanesBlock = 512;
-template <class St>
-struct LanesLds {
+// A strided pass of length N = 64 TPL (radices 8, 8, TPL: 512 and 1024) with
+// one line per lane: a tile of L = 512 / TPL neighbouring lines (each tile
+// position an L-element row segment: 256 bytes for 4-byte storage at 512 and
+// for 8-byte storage at 1024), thread t (of TPL per line) holding positions
+// t + TPL m, m < 64, of its line.  It runs the three Stockham stages of the
+// other kernels butterfly for butterfly, with the same twiddles and the same
+// operations, so its results are bit-identical to theirs; but the first two
+// stages stay in registers.  Stage-0 butterflies j = t + TPL a (a < 8) read
+// positions j + (N/8) q, all the thread's own, and write outputs 8j + p;
+// stage-1 butterfly 8t + r reads outputs 8t + r + (N/8) q of stage 0, i.e.
+// output r of butterfly t + TPL q: the same thread again.  Stage-1 butterfly
+// 8t + r writes 64t + r + 8p; stage 2 (butterflies j < 64, reading j + 64q,
+// q < TPL) needs one element from every thread of the line, so there is one
+// exchange through LDS, made as real parts then imaginary parts through a
+// 128 KiB area; thread t takes butterflies (64/TPL) t + u.  At 512 a
+// wavefront is one t: positions, twiddle indices and the tile origin are
+// uniform, so addresses are a scalar base plus the lane's offset and the
+// stage-2 twiddles sit in scalar registers; at 1024 the two halves of a
+// wavefront are t and t + 1.
+constexpr int kLanesBlock = 512;
+template <int N, class St>
+struct LanesCfg {
     using R = typename St::R;
-    static constexpr size_t kX = (size_t)kLanesN * kLanesL * sizeof(R);   // one component of the tile
-    static constexpr size_t kTw = kX;                                      // w_512^m, m < 512
-    static constexpr size_t kRed = kTw + (size_t)kLanesN * sizeof(cx<R>);  // [8][64] line maxima
-    static constexpr size_t kBytes = kRed + 8 * kLanesL * sizeof(unsigned);
+    static constexpr int TPL = N / 64;              // threads per line
+    static constexpr int L = kLanesBlock / TPL;     // lines per tile
+    static constexpr int NB2 = 64 / TPL;            // stage-2 butterflies per thread
+    static constexpr size_t kX = (size_t)N * L * sizeof(R);              // one component of the tile
+    static constexpr size_t kTw = kX;                                    // w_N^m, m < N
+    static constexpr size_t kRed = kTw + (size_t)N * sizeof(cx<R>);      // [TPL][L] line maxima
+    static constexpr size_t kBytes = kRed + (size_t)TPL * L * sizeof(unsigned);
+    static constexpr RPlan plan = make_rplan(N);
+    static_assert(plan.S == 3 && plan.r[0] == 8 && plan.r[1] == 8 && plan.r[2] == TPL, "radices 8, 8, N/64");
+    static_assert(L == 32 || L == 64, "a tile is one or two lines per wavefront lane group");
 };
 
-template <class St, bool INV, bool NT>
-__global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
+template <int N, class St, bool INV, bool NT>
+__global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
     using R = typename St::R;
-    using Lay = LanesLds<St>;
-    static_assert(sizeof(R) == 4, "FP32 compute: 64 elements per lane in registers");
-    constexpr int N = kLanesN, L = kLanesL;
+    using C = LanesCfg<N, St>;
+    static_assert(sizeof(R) == 4, "FP32 compute: 64 elements per thread in registers");
+    constexpr int TPL = C::TPL, L = C::L, NB2 = C::NB2;
+    constexpr bool kUniform = L == 64;  // a wavefront is one t
     extern __shared__ __align__(16) unsigned char smem[];
     R *xl = reinterpret_cast<R *>(smem);
-    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Lay::kTw);
-    unsigned *red = reinterpret_cast<unsigned *>(smem + Lay::kRed);
+    cx<R> *tws = reinterpret_cast<cx<R> *>(smem + C::kTw);
+    unsigned *red = reinterpret_cast<unsigned *>(smem + C::kRed);
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int s = (int)__builtin_amdgcn_readfirstlane((unsigned)(tid >> 6));
+    const int l = tid % L;
+    // t = t0 + h: t0 uniform in the wavefront, h the half (0 when L = 64)
+    const int t0 = (int)__builtin_amdgcn_readfirstlane((unsigned)((tid >> 6) * (64 / L)));
+    const int h = kUniform ? 0 : (tid >> 5) & 1;
+    const int t = t0 + h;
     {
         const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
         for (int i = tid; i < N; i += kLanesBlock) tws[i] = W[i];
@@ -890,9 +902,12 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
     const long long es = a.es;
     long long tx = tile % a.ntiles, w = tile / a.ntiles;
     const long long gx = G % a.ntiles, gw = G / a.ntiles;
-    const unsigned lane_b = (unsigned)lane * (unsigned)sizeof(typename St::Raw);
+    // the lane's part of an element offset: its line, and its half's share of
+    // the position (h for the loads, NB2 h for the stores)
+    const unsigned lane_b = (unsigned)(((long long)l + h * es) * (long long)sizeof(typename St::Raw));
+    const unsigned lane_s = (unsigned)(((long long)l + (long long)NB2 * h * es) * (long long)sizeof(typename St::Raw));
     for (;;) {
-        const long long q = tx * L + lane;  // this lane's line
+        const long long q = tx * L + l;  // this lane's line
         const bool valid = q < es;
         const long long tbase = tx * L + w * es * N;
         cx<R> v[64];
@@ -905,7 +920,7 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
                     const ExpMap &m = a.em;
                     ep = a.in_exp;
                     ea3 = m.a3;
-                    elane = (unsigned)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2);
+                    elane = (unsigned)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2 + ea3 * h);
                 }
             }
             // every load in flight before the first decode
@@ -913,10 +928,10 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
             int ex[St::kHalf ? 64 : 1];
 #pragma unroll
             for (int m = 0; m < 64; ++m) {
-                const long long pos = s + 8 * m;
-                raw[m] = fetch_at<St, NT>(a.in, tbase + pos * es, lane_b);
+                const long long pos0 = t0 + TPL * m;  // uniform part of the position
+                raw[m] = fetch_at<St, NT>(a.in, tbase + pos0 * es, lane_b);
                 if constexpr (St::kHalf) {
-                    gchar *eb = uniform_gptr(ep, ea3 * pos);
+                    gchar *eb = uniform_gptr(ep, ea3 * pos0);
                     ex[m] = *(const __attribute__((address_space(1))) int8_t *)(eb + lane_reg(elane));
                 }
             }
@@ -927,30 +942,30 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
 #pragma unroll
             for (int m = 0; m < 64; ++m) v[m] = {R(0), R(0)};
         }
-        // stage 0: butterfly s + 8q on v[q + 8p]; output p to v[q + 8p]
+        // stage 0: butterfly t + TPL a on v[a + 8p] (positions t + TPL (a + 8p)); output p to v[a + 8p]
 #pragma unroll
-        for (int qq = 0; qq < 8; ++qq) {
-            cx<R> t[8];
+        for (int aa = 0; aa < 8; ++aa) {
+            cx<R> u8[8];
 #pragma unroll
-            for (int p = 0; p < 8; ++p) t[p] = v[qq + 8 * p];
-            Dft<8, R>::run(t);
+            for (int p = 0; p < 8; ++p) u8[p] = v[aa + 8 * p];
+            Dft<8, R>::run(u8);
 #pragma unroll
-            for (int p = 0; p < 8; ++p) v[qq + 8 * p] = t[p];
+            for (int p = 0; p < 8; ++p) v[aa + 8 * p] = u8[p];
         }
-        // stage 1: butterfly 8s + r on v[8r + p] (output r of stage-0
-        // butterfly s + 8p), twiddles w_64^(p r) = w_512^(8 p r)
+        // stage 1: butterfly 8t + r on v[8r + p] (output r of stage-0
+        // butterfly t + TPL p), twiddles w_N^(p r N / 64)
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            cx<R> t[8];
-            t[0] = v[8 * r];
+            cx<R> u8[8];
+            u8[0] = v[8 * r];
 #pragma unroll
-            for (int p = 1; p < 8; ++p) t[p] = cmul(v[8 * r + p], uniform_cx(tws[8 * p * r]));
-            Dft<8, R>::run(t);
+            for (int p = 1; p < 8; ++p) u8[p] = cmul(v[8 * r + p], uniform_cx(tws[p * r * (N / 64)]));
+            Dft<8, R>::run(u8);
 #pragma unroll
-            for (int p = 0; p < 8; ++p) v[8 * r + p] = t[p];
+            for (int p = 0; p < 8; ++p) v[8 * r + p] = u8[p];
         }
-        // exchange: v[8r + p] is element 64s + r + 8p; stage-2 butterfly
-        // 8s + u reads elements 8s + u + 64p into y[8u + p]
+        // exchange: v[8r + p] is element 64t + r + 8p; stage-2 butterfly
+        // NB2 t + u reads elements NB2 t + u + 64p into y[TPL u + p]
         cx<R> y[64];
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
@@ -959,53 +974,58 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes512(const PassArgs a) {
             for (int r = 0; r < 8; ++r)
 #pragma unroll
                 for (int p = 0; p < 8; ++p)
-                    xl[(64 * s + r + 8 * p) * L + lane] = part ? v[8 * r + p].y : v[8 * r + p].x;
+                    xl[(64 * t + r + 8 * p) * L + l] = part ? v[8 * r + p].y : v[8 * r + p].x;
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < NB2; ++u)
 #pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    const R e = xl[(8 * s + u + 64 * p) * L + lane];
-                    if (part) y[8 * u + p].y = e;
-                    else y[8 * u + p].x = e;
+                for (int p = 0; p < TPL; ++p) {
+                    const R e = xl[(NB2 * t + u + 64 * p) * L + l];
+                    if (part) y[TPL * u + p].y = e;
+                    else y[TPL * u + p].x = e;
                 }
         }
-        // stage 2: butterfly j = 8s + u, twiddles w_512^(p j); outputs j + 64p
+        // stage 2: butterfly j = NB2 t + u, twiddles w_N^(p j); outputs j + 64p
         float mx = 0.0f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = 8 * s + u;
-            cx<R> t[8];
-            t[0] = y[8 * u];
+        for (int u = 0; u < NB2; ++u) {
+            const int j = NB2 * t + u;
+            cx<R> uu[TPL];
+            uu[0] = y[TPL * u];
 #pragma unroll
-            for (int p = 1; p < 8; ++p) t[p] = cmul(y[8 * u + p], uniform_cx(tws[p * j]));
-            Dft<8, R>::run(t);
+            for (int p = 1; p < TPL; ++p) {
+                cx<R> tw = tws[p * j];
+                if constexpr (kUniform) tw = uniform_cx(tw);
+                uu[p] = cmul(y[TPL * u + p], tw);
+            }
+            Dft<TPL, R>::run(uu);
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
-                y[8 * u + p] = t[p];
-                if constexpr (St::kHalf) mx = fmaxf(mx, fmaxf(fabsf(t[p].x), fabsf(t[p].y)));
+            for (int p = 0; p < TPL; ++p) {
+                y[TPL * u + p] = uu[p];
+                if constexpr (St::kHalf) mx = fmaxf(mx, fmaxf(fabsf(uu[p].x), fabsf(uu[p].y)));
             }
         }
         int ex = 0;
         if constexpr (St::kHalf) {
-            // the line's maximum over the eight wavefronts
-            red[s * L + lane] = __float_as_uint(mx);
+            // the line's maximum over its TPL threads
+            red[t * L + l] = __float_as_uint(mx);
             __syncthreads();
-            unsigned mb = red[lane];
+            unsigned mb = red[l];
 #pragma unroll
-            for (int k = 1; k < 8; ++k) mb = max(mb, red[k * L + lane]);
+            for (int k = 1; k < TPL; ++k) mb = max(mb, red[k * L + l]);
             ex = line_exponent(__uint_as_float(mb));
         }
         if (valid) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < NB2; ++u)
 #pragma unroll
-                for (int p = 0; p < 8; ++p) {
-                    const long long pos = 8 * s + u + 64 * p;
-                    store_at<St, NT>(a.out, tbase + pos * es, lane_b, maybe_swap<INV>(y[8 * u + p]), ex);
+                for (int p = 0; p < TPL; ++p) {
+                    // position NB2 t + u + 64 p: NB2 t0 + u + 64 p uniform, NB2 h in lane_s
+                    const long long pos = (long long)NB2 * t0 + u + 64 * p;
+                    store_at<St, NT>(a.out, tbase + pos * es, lane_s, maybe_swap<INV>(y[TPL * u + p]), ex);
                 }
             if constexpr (St::kHalf) {
-                if (s == 0 && a.out_exp) {
+                if (t == 0 && a.out_exp) {
                     const ExpMap &m = a.em;
                     a.out_exp[(q % m.qmod) * m.b0 + (q / m.qmod) * m.b1 + w * m.b2] = (int8_t)ex;
                 }
@@ -1415,22 +1435,23 @@ Entry make_entry(int cand) {
     return e;
 }
 
-// The lane-per-line strided configuration of length 512 (4- or 8-byte storage).
-template <class St, int DT, bool NT>
+// The lane-per-line strided configuration of length N (512 or 1024).
+template <int N, class St, int DT, bool NT>
 Entry make_lanes_entry(int cand) {
-    static_assert(LanesLds<St>::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
+    using C = LanesCfg<N, St>;
+    static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
     Entry e;
-    e.n = kLanesN;
+    e.n = N;
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes512<St, false, NT>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes512<St, true, NT>);
-    e.T = kLanesBlock / kLanesL;
-    e.L = kLanesL;
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NT>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NT>);
+    e.T = C::TPL;
+    e.L = C::L;
     e.block = kLanesBlock;
-    e.lds = LanesLds<St>::kBytes;
-    e.plan = make_rplan(kLanesN);
+    e.lds = C::kBytes;
+    e.plan = C::plan;
     return e;
 }
 

@@ -12,8 +12,8 @@ namespace dev {
 // contiguous: 1 padded LDS lines, 2 no prefetch;
 // strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
 // 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
-// 5 wide tile with non-temporal loads and stores, 6 and 7 (length 512) one line
-// per lane (7 non-temporal); contiguous 3: non-temporal
+// 5 wide tile with non-temporal loads and stores, 6 and 7 (lengths 512 and 1024) one
+// line per lane (7 non-temporal); contiguous 3: non-temporal
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StHalf<true>, 4, kC16B, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StHalf<true>, 4, kC16B, 0, 0, 0, 0>(2),             \
@@ -30,7 +30,8 @@ std::vector<Entry> entries_c16b() {
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384),
         CAND(128, 16, 64, 32, 64), CAND(256, 16, 64, 32, 64), CAND(512, 16, 32, 32, 32), CAND(1024, 32, 16, 64, 16),
-        make_lanes_entry<StHalf<true>, kC16B, false>(6), make_lanes_entry<StHalf<true>, kC16B, true>(7),
+        make_lanes_entry<512, StHalf<true>, kC16B, false>(6), make_lanes_entry<512, StHalf<true>, kC16B, true>(7),
+        make_lanes_entry<1024, StHalf<true>, kC16B, false>(6), make_lanes_entry<1024, StHalf<true>, kC16B, true>(7),
     };
 }
 

@@ -13,8 +13,8 @@ namespace dev {
 // contiguous: 1 padded LDS lines, 2 no prefetch;
 // strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
 // 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
-// 5 wide tile with non-temporal loads and stores, 6 and 7 (length 512) one line
-// per lane (7 non-temporal); contiguous 3: non-temporal;
+// 5 wide tile with non-temporal loads and stores, 6 and 7 (lengths 512 and 1024) one
+// line per lane (7 non-temporal); contiguous 3: non-temporal;
 // fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 1, 1>(1),                 \
@@ -33,7 +33,8 @@ std::vector<Entry> entries_c64() {
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384),
         CAND(128, 16, 32, 32, 32), CAND(256, 16, 32, 32, 32), CAND(512, 16, 32, 32, 32), CAND(1024, 32, 16, 64, 16),
-        make_lanes_entry<StC64, kC64, false>(6), make_lanes_entry<StC64, kC64, true>(7),
+        make_lanes_entry<512, StC64, kC64, false>(6), make_lanes_entry<512, StC64, kC64, true>(7),
+        make_lanes_entry<1024, StC64, kC64, false>(6), make_lanes_entry<1024, StC64, kC64, true>(7),
     };
 }
 
