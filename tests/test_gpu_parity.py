@@ -269,7 +269,9 @@ def test_measure_flag_autotunes_and_records_wisdom(tmp_path, monkeypatch):
     _, y, _ = run_fft(x, C64, flags=croft.CROFT_MEASURE)
     assert oracle.rel_l2(y, oracle.dft3d(seen)) <= TOL[C64]
     lines = [l.split() for l in wisdom.read_text().strip().split("\n")]
-    assert {(int(l[0]), int(l[1])) for l in lines} == {(256, 0), (64, 1), (16, 1)}
+    # strided passes are recorded with their axis (y = 1, z = 2)
+    assert {(int(l[0]), int(l[1]), int(l[5]) if len(l) == 6 else -1) for l in lines} == \
+        {(256, 0, -1), (64, 1, 1), (16, 1, 2)}
     assert np.array_equal(y, ref)
 
 
