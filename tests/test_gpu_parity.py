@@ -127,7 +127,10 @@ def check_half_output(out_bits, out_exp, kind):
 
 
 @pytest.mark.parametrize("dtype", [F16, BF16], ids=["f16", "bf16"])
-@pytest.mark.parametrize("shape", [(40, 48, 64), (27, 60, 45), (1, 16, 1), (6, 1, 100)], ids=str)
+# (512, 3, 40), (1024, 2, 36), (3, 1024, 40): one-line-per-lane strided passes
+# (z at 512 and 1024, y at 1024) with ragged last tiles
+@pytest.mark.parametrize("shape", [(40, 48, 64), (27, 60, 45), (1, 16, 1), (6, 1, 100), (512, 3, 40),
+                                   (1024, 2, 36), (3, 1024, 40)], ids=str)
 def test_half_storage_against_oracle(dtype, shape):
     kind = HALF_KIND[dtype]
     v = synth.normal_c(shape, seed=7)
