@@ -337,6 +337,38 @@ def measure_configs(torch, np, croft, synth):
     return out
 
 
+def measure_shard_share(torch, np, croft, steps):
+    """One GPU's share of a 1024^3 complex64 transform split over 8 GPUs by
+    z-slabs (design only: no second GPU here): the x and y passes of a
+    1024 x 1024 x 128 slab, and the z pass of the 1024 x 128 x 1024 y-slab it
+    holds after the all-to-all, each timed from the library's per-pass
+    events; the exchange itself is modeled (each GPU sends 1/8 of its 1 GiB
+    to each of 7 peers over its own xGMI link at about 153 GB/s)."""
+    out = {}
+    for name, dims, keep in (("xy_slab_1024x1024x128", (1024, 1024, 128), (0, 1)),
+                             ("z_slab_1024x128x1024", (1024, 128, 1024), (2,))):
+        nx, ny, nz = dims
+        d_in = torch.zeros((nz, ny, nx), dtype=torch.complex64, device="cuda")
+        d_in.real.normal_()
+        d_out = torch.empty_like(d_in)
+        plan = croft.croft_plan_create(nx, ny, nz, croft.CROFT_C64, croft.CROFT_FORWARD)
+        info = croft.croft_plan_info(plan)
+        _, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out), steps, 2,
+                             info["npasses"])
+        croft.croft_plan_destroy(plan)
+        axes = [p["axis"] for p in info["passes"]]
+        out[name] = {"pass_ms": {"xyz"[a]: pm[i] for i, a in enumerate(axes) if a in keep}}
+        del d_in, d_out
+        torch.cuda.empty_cache()
+    local = sum(out["xy_slab_1024x1024x128"]["pass_ms"].values()) + out["z_slab_1024x128x1024"]["pass_ms"]["z"]
+    exchange = (2 ** 30 / 8) / 153e9 * 1e3
+    out["local_ms"] = local
+    out["modeled_exchange_ms_each"] = exchange
+    out["modeled_8gpu_ms"] = local + 2 * exchange
+    out["modeled_8gpu_ms_transposed_output"] = local + exchange
+    return out
+
+
 def measure_forms(torch, np, croft, synth, steps):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
@@ -515,6 +547,7 @@ def main():
         line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5))
         line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2)))
         line["configs"] = measure_configs(torch, np, croft, synth)
+        line["forms"]["shard_share_1024cube_8gpu"] = measure_shard_share(torch, np, croft, max(5, args.steps // 5))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, n)
     print(json.dumps(line))
