@@ -58,6 +58,29 @@ def test_shapes_against_oracle(shape, dtype, direction):
     assert np.array_equal(after, seen)                      # out of place keeps the input
 
 
+def _random_shape(rng):
+    # axis lengths: unit, small smooth, the batched lengths, powers of two up
+    # to 1024, and primes (Bluestein); at most about 200 K elements
+    pool = [1, 2, 3, 4, 5, 6, 8, 9, 12, 15, 16, 25, 27, 32, 48, 60, 64, 72, 80, 96, 100, 128, 256, 512, 1024,
+            7, 11, 13, 17, 31, 37, 97]
+    while True:
+        shape = tuple(int(v) for v in rng.choice(pool, size=3))
+        if np.prod(shape) <= 200_000:
+            return shape
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_random_shapes_against_oracle(case):
+    rng = np.random.Generator(np.random.PCG64(1000 + case))
+    shape = _random_shape(rng)
+    dtype = (C64, C128)[int(rng.integers(2))]
+    direction = (FWD, BWD)[int(rng.integers(2))]
+    print(f"case {case}: shape {shape} dtype {dtype} dir {direction}", flush=True)
+    x = synth.normal_c(shape, seed=case)
+    seen, y, _ = run_fft(x, dtype, direction)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, direction)) <= TOL[dtype], (shape, dtype, direction)
+
+
 @pytest.mark.parametrize("dtype", [C64, C128], ids=["c64", "c128"])
 def test_in_place_equals_out_of_place_bitwise(dtype):
     x = synth.normal_c((40, 36, 50), seed=3)
