@@ -238,12 +238,14 @@ def test_execute_argument_errors_on_device():
     croft.croft_plan_destroy(hplan)
 
 
+@pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
 @pytest.mark.parametrize("dtype", [C64, F16], ids=["c64", "f16"])
 @pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20), (4, 512, 80)], ids=str)
-def test_every_compiled_candidate_gives_identical_bits(dtype, shape, tmp_path, monkeypatch):
+def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, tmp_path, monkeypatch):
     """Every autotuner candidate (and persistent-grid size) runs the same
-    arithmetic in the same order, so the outputs agree bit for bit; the
-    default candidate is checked against the oracle elsewhere."""
+    arithmetic in the same order, so the outputs agree bit for bit, in both
+    directions (each has its own instantiation); the default candidate is
+    checked against the oracle elsewhere."""
     wisdom = tmp_path / "wisdom.txt"
     monkeypatch.setenv("CROFT_WISDOM", str(wisdom))
     nz, ny, nx = shape
@@ -258,7 +260,7 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, tmp_path, m
     def run():
         out = torch.full_like(x, float("nan"))
         eout = torch.full((ny, nx), 99, dtype=torch.int8, device="cuda")
-        plan = croft.croft_plan_create(nx, ny, nz, dtype, FWD)
+        plan = croft.croft_plan_create(nx, ny, nz, dtype, direction)
         info = croft.croft_plan_info(plan)
         if dtype == C64:
             croft.croft_execute(plan, x, out)
