@@ -186,6 +186,16 @@ def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
     assert [p["candidate"] for p in passes][1:] == ["4", "2"] and passes[2]["waves"] == "2"
 
 
+def test_builtin_one_line_per_lane_at_1024(tmp_path, monkeypatch):
+    # complex64 strided passes of length 1024: 16 threads per line, 32-line
+    # tiles (256-byte rows) in 512-thread blocks, both axes and directions
+    for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
+        passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 1024, 1024, 1024, croft.CROFT_C64, direction)
+        for p in passes[1:]:
+            assert (p["candidate"], p["T"], p["L"], p["block"]) == ("7", "16", "32", "512")
+            assert int(p["lds"]) <= 160 * 1024
+
+
 def test_wisdom_unknown_candidate_falls_back_to_default(tmp_path, monkeypatch):
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 9 1\n", 512, 512, 512)
     assert passes[1]["candidate"] == "0"
