@@ -5,7 +5,7 @@ three axis passes with their in-LDS transposes) on a PME-style charge grid
 already resident in HBM; `value` is GFLOP/s by the 5 N log2 N convention.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--size 512] [--slabs K]
-                  [--no-cpu-baseline] [--no-forms] [--calibrate-copy]
+                  [--no-cpu-baseline] [--no-forms] [--calibrate-copy] [--only-form half]
 
 The dominant kernel's roofline uses HIP events recorded by the library around
 each pass launch on the stream the pass runs on, over the timed region.
@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--only-form", choices=["half"], default=None,
+                    help="time one form alone (for profiling) and print it")
     return ap.parse_args()
 
 
@@ -369,10 +371,10 @@ def measure_shard_share(torch, np, croft, steps):
     return out
 
 
-def measure_forms(torch, np, croft, synth, steps):
+def measure_forms(torch, np, croft, synth, steps, only=None):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
-    against that form."""
+    against that form (only="half": the half-storage forms alone)."""
     out = {}
     n = 512
     N = n ** 3
@@ -418,6 +420,8 @@ def measure_forms(torch, np, croft, synth, steps):
         torch.cuda.empty_cache()
     del v, orig_out
     torch.cuda.empty_cache()
+    if only == "half":
+        return out
     # batched: 64 uneven PME grids
     dims = synth.batch_dims(4)
     grids = [synth.pme_grid(int(a), int(b), int(c), seed=400 + i)[0] for i, (a, b, c) in enumerate(dims)]
@@ -488,6 +492,9 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy(torch, args.steps, args.warmup)
+        return
+    if args.only_form == "half":
+        print(json.dumps({"forms": measure_forms(torch, np, croft, synth, args.steps, only="half")}))
         return
 
     n = args.size

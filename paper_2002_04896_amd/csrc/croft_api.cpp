@@ -159,21 +159,21 @@ int build_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<P
         p.cfg.grid_waves = waves;
         if (half) {
             ExpMap &m = p.em;
-            const long long big = 1LL << 40;
+            const long long big = 1LL << 31;  // no wrap
             if (axis == 0) {
                 // lines l = y + ny z; input exponents per x-line; output per x-line
-                m.qmod = big; m.a0 = 1; m.b0 = 1;
+                set_exp_qmod(m, big); m.a0 = 1; m.b0 = 1;
             } else if (axis == 1) {
                 if (p.kind == kStrided) {  // q = x, w = z, j = y
-                    m.qmod = big; m.a2 = g.ny; m.a3 = 1; m.b0 = 1; m.b2 = g.nx;
+                    set_exp_qmod(m, big); m.a2 = g.ny; m.a3 = 1; m.b0 = 1; m.b2 = g.nx;
                 } else {                   // nx == 1: q = z, j = y
-                    m.qmod = big; m.a0 = g.ny; m.a3 = 1; m.b0 = 1;
+                    set_exp_qmod(m, big); m.a0 = g.ny; m.a3 = 1; m.b0 = 1;
                 }
             } else {
                 if (p.kind == kStrided) {  // q = x + nx y, j = z
-                    m.qmod = g.nx; m.a0 = 1; m.a3 = g.nx; m.b0 = 1; m.b1 = g.nx;
+                    set_exp_qmod(m, g.nx); m.a0 = 1; m.a3 = g.nx; m.b0 = 1; m.b1 = g.nx;
                 } else {                   // nx == ny == 1: one line, j = z
-                    m.qmod = big; m.a3 = 1; m.b0 = 1;
+                    set_exp_qmod(m, big); m.a3 = 1; m.b0 = 1;
                 }
             }
         }
@@ -318,6 +318,11 @@ int check_exp_maps(const Geometry &g, const std::vector<PassLaunch> &ps) {
     const long long sizes[4] = {(long long)g.ny * g.nz, (long long)g.ny * g.nz, (long long)g.nx * g.nz,
                                 (long long)g.nx * g.ny};
     for (size_t i = 0; i < ps.size(); ++i) {
+        // the kernels divide q by qmod with the map's multiply and shift,
+        // exact for q < 2^31
+        const long long qmax = ps[i].kind == kContiguous ? ps[i].nlines - 1 : ps[i].es - 1;
+        if (qmax >= (1LL << 31))
+            return fail(CROFT_ERR_INTERNAL, "line index of pass %zu exceeds 2^31 - 1", i);
         long long imax, omax;
         exp_extent(ps[i], &imax, &omax);
         if (imax >= sizes[i] || omax >= sizes[i + 1])

@@ -322,6 +322,17 @@ __device__ __forceinline__ unsigned lanes_max_u32(unsigned v) {
     return v;
 }
 
+// (q % qmod) c0 + (q / qmod) c1 + w c2 for a line q < 2^31, in 32 bits
+// (exponent arrays hold fewer than 2^31 entries): the division is the
+// multiply and shift the exponent map carries.
+__device__ __forceinline__ unsigned exp_line_index(const ExpMap &m, long long q, long long w, long long c0,
+                                                   long long c1, long long c2) {
+    const unsigned uq = (unsigned)q;
+    const unsigned d = (unsigned)(((unsigned long long)uq * m.qmul) >> m.qshift);
+    const unsigned r = uq - d * (unsigned)m.qmod;
+    return r * (unsigned)c0 + d * (unsigned)c1 + (unsigned)w * (unsigned)c2;
+}
+
 // The inverse transform is swap(DFT(swap(x))) with swap(a + ib) = b + ia.
 template <bool INV, typename R>
 __device__ __forceinline__ cx<R> maybe_swap(cx<R> v) {
@@ -533,21 +544,23 @@ __device__ __forceinline__ unsigned lane_reg(unsigned v) {
     return r;
 }
 
+// base: the tile's origin, made uniform once per tile (uniform_gptr); the
+// uniform element offset is then added in scalar registers.
 template <class St, bool NT = false>
-__device__ __forceinline__ typename St::Raw fetch_at(const void *p, long long uniform_elem, unsigned lane_bytes) {
+__device__ __forceinline__ typename St::Raw fetch_at(gchar *base, long long uniform_elem, unsigned lane_bytes) {
     using Raw = typename St::Raw;
     lane_bytes = lane_reg(lane_bytes);
-    gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(Raw));
+    gchar *b = base + uniform_elem * (long long)sizeof(Raw);
     const __attribute__((address_space(1))) Raw *q = (const __attribute__((address_space(1))) Raw *)(b + lane_bytes);
     if constexpr (NT) return __builtin_nontemporal_load(q);
     return *q;
 }
 
 template <class St, bool NT = false>
-__device__ __forceinline__ void store_at(void *p, long long uniform_elem, unsigned lane_bytes,
+__device__ __forceinline__ void store_at(gchar *base, long long uniform_elem, unsigned lane_bytes,
                                          cx<typename St::R> v, int ex) {
     lane_bytes = lane_reg(lane_bytes);
-    gchar *b = uniform_gptr(p, uniform_elem * (long long)sizeof(typename St::Raw));
+    gchar *b = base + uniform_elem * (long long)sizeof(typename St::Raw);
     if constexpr (NT) {
         __builtin_nontemporal_store(St::pack(v, ex), (__attribute__((address_space(1))) typename St::Raw *)(b + lane_bytes));
     } else {
@@ -575,22 +588,26 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
             const ExpMap &m = a.em;
             ep = a.in_exp;
             ea3 = m.a3;
-            elane = (unsigned)((c.q % m.qmod) * m.a0 + (c.q / m.qmod) * m.a1 + c.w * m.a2 + ea3 * t);
+            elane = exp_line_index(m, c.q, c.w, m.a0, m.a1, m.a2) + (unsigned)ea3 * (unsigned)t;
         }
     }
+    // contiguous tiles: the tile origin made uniform once per tile (left in
+    // each access, the compiler computes it in vector registers there)
+    const long long ut = KIND == kContiguous ? 0 : c.tbase;
+    gchar *const ib = uniform_gptr(a.in, (c.tbase - ut) * (long long)sizeof(typename St::Raw));
+    gchar *const eb = uniform_gptr(ep, 0);
 #pragma unroll
     for (int b = 0; b < TL::B0; ++b) {
         const int j = t + b * Cfg::T;
         if ((TL::NB0 % Cfg::T) == 0 || j < TL::NB0) {
 #pragma unroll
             for (int q = 0; q < TL::R0; ++q) {
-                const long long u = c.tbase + (long long)(b * Cfg::T + q * TL::NB0) * es;
-                const typename St::Raw r = fetch_at<St, Cfg::kNT>(a.in, u, lane);
+                const long long u = ut + (long long)(b * Cfg::T + q * TL::NB0) * es;
+                const typename St::Raw r = fetch_at<St, Cfg::kNT>(ib, u, lane);
                 int ex = 0;
-                if constexpr (St::kHalf) {
-                    gchar *eb = uniform_gptr(ep, ea3 * (b * Cfg::T + q * TL::NB0));
-                    ex = *(const __attribute__((address_space(1))) int8_t *)(eb + lane_reg(elane));
-                }
+                if constexpr (St::kHalf)
+                    ex = *(const __attribute__((address_space(1))) int8_t *)(eb + ea3 * (b * Cfg::T + q * TL::NB0) +
+                                                                              lane_reg(elane));
                 if constexpr (TL::kRaw) {
                     tl.e[b][q] = r;
                     if constexpr (St::kHalf) tl.ex[b][q] = ex;
@@ -712,14 +729,16 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
             ex_out = ex;
         }
         if (c.valid) {
+            const long long ut = KIND == kContiguous ? 0 : c.tbase;
+            gchar *const ob = uniform_gptr(a.out, (c.tbase - ut) * (long long)sizeof(typename St::Raw));
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 const int j = t + b * T;
                 if (!kGuard || j < NB) {
 #pragma unroll
                     for (int q = 0; q < RAD; ++q) {
-                        const long long u = c.tbase + (long long)(b * T + q * NB) * es;
-                        store_at<St, Cfg::kNT>(a.out, u, lane, maybe_swap<INV>(v[b][q]), ex);
+                        const long long u = ut + (long long)(b * T + q * NB) * es;
+                        store_at<St, Cfg::kNT>(ob, u, lane, maybe_swap<INV>(v[b][q]), ex);
                     }
                 }
             }
@@ -824,7 +843,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
         if constexpr (St::kHalf) {
             if (c.valid && t == 0 && a.out_exp) {
                 const ExpMap &m = a.em;
-                a.out_exp[(c.q % m.qmod) * m.b0 + (c.q / m.qmod) * m.b1 + c.w * m.b2] = (int8_t)ex;
+                a.out_exp[exp_line_index(m, c.q, c.w, m.b0, m.b1, m.b2)] = (int8_t)ex;
             }
         }
         if (!more) break;
@@ -859,6 +878,17 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
 // stage-2 twiddles sit in scalar registers; at 1024 the two halves of a
 // wavefront are t and t + 1.
 constexpr int kLanesBlock = 512;
+
+// A zero the compiler cannot see through, made once per tile.  Added to the
+// twiddle indices and to the strides, it keeps the twiddle reads and the
+// 64-bit offsets of the tile's 128 accesses in the tile loop: hoisted out
+// of it as loop invariants, they would stay live across the whole loop,
+// more than the scalar registers hold, and spill.
+__device__ __forceinline__ int opaque_zero() {
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
 template <int N, class St>
 struct LanesCfg {
     using R = typename St::R;
@@ -907,6 +937,7 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
     const unsigned lane_b = (unsigned)(((long long)l + h * es) * (long long)sizeof(typename St::Raw));
     const unsigned lane_s = (unsigned)(((long long)l + (long long)NB2 * h * es) * (long long)sizeof(typename St::Raw));
     for (;;) {
+        const int tz = opaque_zero();
         const long long q = tx * L + l;  // this lane's line
         const bool valid = q < es;
         const long long tbase = tx * L + w * es * N;
@@ -920,20 +951,21 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
                     const ExpMap &m = a.em;
                     ep = a.in_exp;
                     ea3 = m.a3;
-                    elane = (unsigned)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2 + ea3 * h);
+                    elane = exp_line_index(m, q, w, m.a0, m.a1, m.a2) + (unsigned)ea3 * (unsigned)h;
                 }
             }
             // every load in flight before the first decode
             typename St::Raw raw[64];
             int ex[St::kHalf ? 64 : 1];
+            gchar *const ib = uniform_gptr(a.in, tbase * (long long)sizeof(typename St::Raw));
+            gchar *const eb = uniform_gptr(ep, 0);
+            const long long est = es + tz, ea3t = ea3 + tz;
 #pragma unroll
             for (int m = 0; m < 64; ++m) {
-                const long long pos0 = t0 + TPL * m;  // uniform part of the position
-                raw[m] = fetch_at<St, NT>(a.in, tbase + pos0 * es, lane_b);
-                if constexpr (St::kHalf) {
-                    gchar *eb = uniform_gptr(ep, ea3 * pos0);
-                    ex[m] = *(const __attribute__((address_space(1))) int8_t *)(eb + lane_reg(elane));
-                }
+                const long long pos0 = t0 + tz + TPL * m;  // uniform part of the position
+                raw[m] = fetch_at<St, NT>(ib, pos0 * est, lane_b);
+                if constexpr (St::kHalf)
+                    ex[m] = *(const __attribute__((address_space(1))) int8_t *)(eb + ea3t * pos0 + lane_reg(elane));
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -959,7 +991,7 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
             cx<R> u8[8];
             u8[0] = v[8 * r];
 #pragma unroll
-            for (int p = 1; p < 8; ++p) u8[p] = cmul(v[8 * r + p], uniform_cx(tws[p * r * (N / 64)]));
+            for (int p = 1; p < 8; ++p) u8[p] = cmul(v[8 * r + p], tws[p * r * (N / 64) + tz]);
             Dft<8, R>::run(u8);
 #pragma unroll
             for (int p = 0; p < 8; ++p) v[8 * r + p] = u8[p];
@@ -994,9 +1026,7 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
             uu[0] = y[TPL * u];
 #pragma unroll
             for (int p = 1; p < TPL; ++p) {
-                cx<R> tw = tws[p * j];
-                if constexpr (kUniform) tw = uniform_cx(tw);
-                uu[p] = cmul(y[TPL * u + p], tw);
+                uu[p] = cmul(y[TPL * u + p], tws[p * j + tz]);
             }
             Dft<TPL, R>::run(uu);
 #pragma unroll
@@ -1016,18 +1046,20 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
             ex = line_exponent(__uint_as_float(mb));
         }
         if (valid) {
+            gchar *const ob = uniform_gptr(a.out, tbase * (long long)sizeof(typename St::Raw));
+            const long long est = es + tz;
 #pragma unroll
             for (int u = 0; u < NB2; ++u)
 #pragma unroll
                 for (int p = 0; p < TPL; ++p) {
                     // position NB2 t + u + 64 p: NB2 t0 + u + 64 p uniform, NB2 h in lane_s
-                    const long long pos = (long long)NB2 * t0 + u + 64 * p;
-                    store_at<St, NT>(a.out, tbase + pos * es, lane_s, maybe_swap<INV>(y[TPL * u + p]), ex);
+                    const long long pos = (long long)NB2 * (t0 + tz) + u + 64 * p;
+                    store_at<St, NT>(ob, pos * est, lane_s, maybe_swap<INV>(y[TPL * u + p]), ex);
                 }
             if constexpr (St::kHalf) {
                 if (t == 0 && a.out_exp) {
                     const ExpMap &m = a.em;
-                    a.out_exp[(q % m.qmod) * m.b0 + (q / m.qmod) * m.b1 + w * m.b2] = (int8_t)ex;
+                    a.out_exp[exp_line_index(m, q, w, m.b0, m.b1, m.b2)] = (int8_t)ex;
                 }
             }
         }

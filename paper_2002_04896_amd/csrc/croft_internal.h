@@ -60,11 +60,27 @@ struct KernelConfig {
 // with line-block index w (strided only, 0 otherwise):
 //   input exponent index  = (q % qmod) * a0 + (q / qmod) * a1 + w * a2 + j * a3
 //   output exponent index = (q % qmod) * b0 + (q / qmod) * b1 + w * b2
+// Every q is below 2^31 (grids hold fewer than 2^31 elements), so q / qmod is
+// (q qmul) >> qshift with qmul = floor(2^(31 + l) / qmod) + 1 and
+// l = ceil(log2 qmod), qshift = 31 + l: exact for q < 2^31 (Granlund and
+// Montgomery, division by invariant integers using multiplication, 1994,
+// theorem 4.2).  qmod = 2^31 leaves q whole (no wrap); set it with
+// set_exp_qmod.
 struct ExpMap {
-    long long qmod = 1LL << 40;
+    long long qmod = 1LL << 31;
+    unsigned long long qmul = (1ULL << 31) + 1;
+    int qshift = 62;
     long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     long long b0 = 0, b1 = 0, b2 = 0;
 };
+
+inline void set_exp_qmod(ExpMap &m, long long qmod) {
+    int l = 0;
+    while ((1LL << l) < qmod) ++l;
+    m.qmod = qmod;
+    m.qmul = (unsigned long long)(((unsigned __int128)1 << (31 + l)) / (unsigned long long)qmod) + 1;
+    m.qshift = 31 + l;
+}
 
 // One launch of one pass over (a slab of) a grid.
 struct PassLaunch {

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
     int ebase = 0;
     if constexpr (St::kHalf) {
         const ExpMap &m = a.em;
-        ebase = (int)((q % m.qmod) * m.a0 + (q / m.qmod) * m.a1 + w * m.a2);
+        ebase = (int)exp_line_index(m, q, w, m.a0, m.a1, m.a2);
         if (active && t == 0) red[l] = 0u;
     }
     // load the line into buf0 (consecutive t read consecutive e)
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
         if (active) ex = line_exponent(__uint_as_float(red[l]));
         if (valid && t == 0 && a.out_exp) {
             const ExpMap &m = a.em;
-            a.out_exp[(q % m.qmod) * m.b0 + (q / m.qmod) * m.b1 + w * m.b2] = (int8_t)ex;
+            a.out_exp[exp_line_index(m, q, w, m.b0, m.b1, m.b2)] = (int8_t)ex;
         }
     }
     if (valid) {
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) fft_bluestein(const PassArgs a) {
     int ebase = 0;
     if constexpr (St::kHalf) {
         const ExpMap &mp = a.em;
-        ebase = (int)((q % mp.qmod) * mp.a0 + (q / mp.qmod) * mp.a1 + w * mp.a2);
+        ebase = (int)exp_line_index(mp, q, w, mp.a0, mp.a1, mp.a2);
         if (active && t == 0) red[l] = 0u;
     }
     // chirped line, zero-padded to m
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) fft_bluestein(const PassArgs a) {
         if (active) ex = line_exponent(__uint_as_float(red[l]));
         if (valid && t == 0 && a.out_exp) {
             const ExpMap &mp = a.em;
-            a.out_exp[(q % mp.qmod) * mp.b0 + (q / mp.qmod) * mp.b1 + w * mp.b2] = (int8_t)ex;
+            a.out_exp[exp_line_index(mp, q, w, mp.b0, mp.b1, mp.b2)] = (int8_t)ex;
         }
     }
     if (valid) {
