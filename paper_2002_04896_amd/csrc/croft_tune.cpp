@@ -51,31 +51,34 @@ const Builtin kBuiltin[] = {
     {64, 0, 2, 0, 0}, {64, 1, 2, 0, 1}, {72, 0, 2, 0, 2}, {72, 1, 2, 0, 0}, {80, 0, 2, 0, 4}, {80, 1, 2, 0, 2},
     {96, 0, 2, 0, 4}, {96, 1, 2, 0, 0}, {100, 0, 2, 0, 1}, {100, 1, 2, 0, 4}, {128, 0, 2, 1, 1},
     {128, 1, 2, 1, 4}, {256, 0, 2, 1, 0}, {256, 1, 2, 2, 1}, {384, 0, 2, 0, 0}, {384, 1, 2, 0, 1},
-    {512, 0, 2, 1, 4}, {512, 1, 2, 5, 0}, {1024, 0, 2, 3, 4}, {1024, 1, 2, 7, 1},
+    {512, 0, 2, 1, 4}, {512, 1, 2, 6, 1}, {1024, 0, 2, 3, 4}, {1024, 1, 2, 7, 1},
     // BF16 storage
     {32, 0, 3, 0, 0}, {32, 1, 3, 0, 2}, {48, 0, 3, 0, 2}, {48, 1, 3, 0, 2}, {60, 0, 3, 0, 4}, {60, 1, 3, 0, 1},
     {64, 0, 3, 0, 2}, {64, 1, 3, 0, 4}, {72, 0, 3, 0, 4}, {72, 1, 3, 0, 4}, {80, 0, 3, 0, 1}, {80, 1, 3, 0, 2},
     {96, 0, 3, 0, 0}, {96, 1, 3, 0, 2}, {100, 0, 3, 0, 2}, {100, 1, 3, 0, 0}, {128, 0, 3, 1, 2},
     {128, 1, 3, 1, 0}, {256, 0, 3, 1, 0}, {256, 1, 3, 2, 1}, {384, 0, 3, 0, 0}, {384, 1, 3, 0, 1},
-    {512, 0, 3, 1, 4}, {512, 1, 3, 5, 0}, {1024, 0, 3, 3, 4}, {1024, 1, 3, 7, 1},
+    {512, 0, 3, 1, 4}, {512, 1, 3, 6, 1}, {1024, 0, 3, 3, 4}, {1024, 1, 3, 7, 1},
 };
 
 // Forward-only choices, looked up before the table above by forward plans:
 // where the best configuration for both directions together is not the best
-// forward one (512 strided complex64: the 1024-thread wide tile is the
-// fastest forward but spills in its inverse).
+// forward one (512 strided complex64 passes with no per-axis choice, such as
+// the convolution plan's: the 1024-thread wide tile is the fastest forward
+// but spills in its inverse).
 const Builtin kBuiltinForward[] = {
     {512, 1, 0, 2, 1},
 };
 
-// Per-axis choices (n kind dtype axis candidate waves): 512 strided with
-// 16-bit storage, where the y pass (2 KiB stride) is fastest with the
-// 32-line tiles and the z pass (1 MiB stride) with one line per lane.
+// Per-axis choices (n kind dtype axis candidate waves), looked up before
+// the two tables above: 512 strided complex64, one line per lane on both
+// axes, the z pass (2 MiB stride) with non-temporal accesses and the y pass
+// (4 KiB stride) without.
 struct BuiltinAxis {
     int n, kind, dtype, axis, cand, waves;
 };
 const BuiltinAxis kBuiltinAxis[] = {
-    {512, 1, 2, 1, 5, 2}, {512, 1, 2, 2, 6, 1}, {512, 1, 3, 1, 5, 2}, {512, 1, 3, 2, 6, 1},
+    {512, 1, 0, 1, 6, 4},
+    {512, 1, 0, 2, 7, 4},
 };
 
 std::mutex g_mu;
@@ -118,18 +121,18 @@ bool wisdom_lookup(int n, int kind, int dtype, int dir, int axis, int *cand, int
             return true;
         }
     }
-    if (dir == -1) {
-        for (const Builtin &b : kBuiltinForward) {
-            if (b.n == n && b.kind == kind && b.dtype == dtype) {
+    if (axis >= 0) {
+        for (const BuiltinAxis &b : kBuiltinAxis) {
+            if (b.n == n && b.kind == kind && b.dtype == dtype && b.axis == axis) {
                 *cand = b.cand;
                 *waves = b.waves;
                 return true;
             }
         }
     }
-    if (axis >= 0) {
-        for (const BuiltinAxis &b : kBuiltinAxis) {
-            if (b.n == n && b.kind == kind && b.dtype == dtype && b.axis == axis) {
+    if (dir == -1) {
+        for (const Builtin &b : kBuiltinForward) {
+            if (b.n == n && b.kind == kind && b.dtype == dtype) {
                 *cand = b.cand;
                 *waves = b.waves;
                 return true;

@@ -150,16 +150,19 @@ def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
     return parse_describe(croft.croft_plan_describe(*args))[1]
 
 
-def test_builtin_wisdom_picks_wide_strided_tiles(tmp_path, monkeypatch):
-    # measured choices, all with 32-line (256-byte row) tiles: forward plans
-    # take the 1024-thread tile (32 x 16 elements), fastest forward; backward
-    # plans the 512-thread tile (16 x 32), whose inverse does not spill
-    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512)
+def test_builtin_wisdom_picks_one_line_per_lane_at_512(tmp_path, monkeypatch):
+    # complex64 strided passes of length 512, both directions: one line per
+    # lane (8 threads per line, 64-line tiles of 256-byte rows, 512-thread
+    # blocks) on both axes, the z pass with non-temporal accesses
+    for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
+        passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64, direction)
+        assert [p["candidate"] for p in passes][1:] == ["6", "7"]
+        for p in passes[1:]:
+            assert (p["T"], p["L"], p["block"], p["waves"]) == ("8", "64", "512", "4")
+    # a wisdom line for any axis comes before the built-in per-axis choices
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 2 1\n", 512, 512, 512)
     assert [p["candidate"] for p in passes][1:] == ["2", "2"]
     assert passes[1]["L"] == "32" and passes[1]["T"] == "32"
-    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, 0, 1)
-    assert [p["candidate"] for p in passes][1:] == ["4", "4"]
-    assert passes[1]["L"] == "32" and passes[1]["T"] == "16"
 
 
 def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
@@ -172,18 +175,25 @@ def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
 
 
 def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
-    # 16-bit storage at 512: the built-in choices differ between the y pass
-    # (32-line tiles) and the z pass (one line per lane)
-    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C16F)
-    assert [p["candidate"] for p in passes][1:] == ["5", "6"]
-    assert passes[2]["L"] == "64" and passes[2]["T"] == "8"
+    # complex64 at 512: the built-in choices differ between the y pass (one
+    # line per lane) and the z pass (the same kernel, non-temporal)
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64)
+    assert [p["candidate"] for p in passes][1:] == ["6", "7"]
     # a file line for any axis comes before the built-in per-axis choices ...
-    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 2 4 1\n", 512, 512, 512, croft.CROFT_C16F)
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 4 1\n", 512, 512, 512, croft.CROFT_C64)
     assert [p["candidate"] for p in passes][1:] == ["4", "4"]
     # ... and a line for the pass's own axis before one for any axis
-    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 2 4 1\n512 1 2 2 2 2\n", 512, 512, 512,
-                                   croft.CROFT_C16F)
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 4 1\n512 1 0 2 2 2\n", 512, 512, 512,
+                                   croft.CROFT_C64)
     assert [p["candidate"] for p in passes][1:] == ["4", "2"] and passes[2]["waves"] == "2"
+
+
+def test_builtin_half_storage_one_line_per_lane_at_512(tmp_path, monkeypatch):
+    # 16-bit storage at 512: one line per lane on both strided axes
+    for dt in (croft.CROFT_C16F, croft.CROFT_C16B):
+        passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, dt)
+        assert [p["candidate"] for p in passes][1:] == ["6", "6"]
+        assert all((p["T"], p["L"]) == ("8", "64") for p in passes[1:])
 
 
 def test_builtin_one_line_per_lane_at_1024(tmp_path, monkeypatch):
