@@ -245,9 +245,6 @@ struct StC128 {
 __device__ __forceinline__ float f16_bits_to_float(unsigned short b) {
     return __half2float(__ushort_as_half(b));
 }
-__device__ __forceinline__ unsigned short float_to_f16_bits(float f) {
-    return __half_as_ushort(__float2half_rn(f));
-}
 __device__ __forceinline__ float bf16_bits_to_float(unsigned short b) {
     return __uint_as_float(static_cast<unsigned>(b) << 16);
 }
@@ -258,6 +255,13 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned floats_to_bf16x2_bits(float lo, float hi) {
     const f32x2 w = {lo, hi};
     return __builtin_bit_cast(unsigned, __builtin_convertvector(w, bf16x2));
+}
+// The same to two binary16, rounded to nearest, ties to even: one
+// v_cvt_pk_f16_f32 on gfx950.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned floats_to_f16x2_bits(float lo, float hi) {
+    const f32x2 w = {lo, hi};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(w, f16x2));
 }
 
 template <bool BF>
@@ -280,9 +284,7 @@ struct StHalf {
     static __device__ __forceinline__ unsigned encode(cx<R> v, int e) {
         const float re = ldexpf(v.x, -e), im = ldexpf(v.y, -e);
         if constexpr (BF) return floats_to_bf16x2_bits(re, im);
-        const unsigned lo = float_to_f16_bits(re);
-        const unsigned hi = float_to_f16_bits(im);
-        return lo | (hi << 16);
+        return floats_to_f16x2_bits(re, im);
     }
     static __device__ __forceinline__ void store(void *p, long long i, cx<R> v, int e) {
         reinterpret_cast<unsigned *>(p)[i] = encode(v, e);
