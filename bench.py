@@ -16,6 +16,8 @@ the plain complex64 form on the same GPU with its error against it, and the
 smaller cubes (32^3 latency; 256^3 and 384^3 forward and inverse, warm and
 with the Infinity Cache flushed) under "configs" (`--no-forms` skips both).
 The effective rate is also given as a fraction of a measured device copy.
+`--only-form half` runs only the FP16 and BF16 storage forms (each beside a
+complex64 transform of the same values) and prints them, for counter runs.
 """
 from __future__ import annotations
 
