@@ -861,9 +861,10 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
 
 // ------------------------------------------------- lane-per-line strided pass
 // A strided pass of length N = 64 TPL (radices 8, 8, TPL: 512 and 1024) with
-// one line per lane: a tile of L = 512 / TPL neighbouring lines (each tile
-// position an L-element row segment: 256 bytes for 4-byte storage at 512 and
-// for 8-byte storage at 1024), thread t (of TPL per line) holding positions
+// one line per lane: a tile of L = BLOCK / TPL neighbouring lines (BLOCK =
+// 512 threads, or 256 at 512; each tile position an L-element row segment:
+// 256 bytes for 4-byte storage at 512 and for 8-byte storage at 1024 or in
+// 256-thread blocks), thread t (of TPL per line) holding positions
 // t + TPL m, m < 64, of its line.  It runs the three Stockham stages of the
 // other kernels butterfly for butterfly, with the same twiddles and the same
 // operations, so its results are bit-identical to theirs; but the first two
@@ -873,12 +874,14 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
 // output r of butterfly t + TPL q: the same thread again.  Stage-1 butterfly
 // 8t + r writes 64t + r + 8p; stage 2 (butterflies j < 64, reading j + 64q,
 // q < TPL) needs one element from every thread of the line, so there is one
-// exchange through LDS, made as real parts then imaginary parts through a
-// 128 KiB area; thread t takes butterflies (64/TPL) t + u.  At 512 a
-// wavefront is one t: positions, twiddle indices and the tile origin are
-// uniform, so addresses are a scalar base plus the lane's offset and the
-// stage-2 twiddles sit in scalar registers; at 1024 the two halves of a
-// wavefront are t and t + 1.
+// exchange through LDS, made as real parts then imaginary parts through an
+// area of N L floats (128 KiB in 512-thread blocks); thread t takes
+// butterflies (64/TPL) t + u.  With 64-line tiles a wavefront is one t:
+// positions, twiddle indices and the tile origin are uniform, so addresses
+// are a scalar base plus the lane's offset; with 32-line tiles the two
+// halves of a wavefront are t and t + 1.  A 256-thread block at 512
+// (32-line tiles, 256-byte rows of complex64, a 64 KiB exchange area) lets
+// two blocks share a CU, each overlapping its loads with the other's stages.
 constexpr int kLanesBlock = 512;
 
 // A zero the compiler cannot see through, made once per tile.  Added to the
@@ -891,11 +894,11 @@ __device__ __forceinline__ int opaque_zero() {
     asm volatile("s_mov_b32 %0, 0" : "=s"(z));
     return z;
 }
-template <int N, class St>
+template <int N, class St, int BLOCK = kLanesBlock>
 struct LanesCfg {
     using R = typename St::R;
     static constexpr int TPL = N / 64;              // threads per line
-    static constexpr int L = kLanesBlock / TPL;     // lines per tile
+    static constexpr int L = BLOCK / TPL;           // lines per tile
     static constexpr int NB2 = 64 / TPL;            // stage-2 butterflies per thread
     static constexpr size_t kX = (size_t)N * L * sizeof(R);              // one component of the tile
     static constexpr size_t kTw = kX;                                    // w_N^m, m < N
@@ -906,10 +909,10 @@ struct LanesCfg {
     static_assert(L == 32 || L == 64, "a tile is one or two lines per wavefront lane group");
 };
 
-template <int N, class St, bool INV, bool NT>
-__global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
+template <int N, class St, bool INV, bool NT, int BLOCK = kLanesBlock>
+__global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     using R = typename St::R;
-    using C = LanesCfg<N, St>;
+    using C = LanesCfg<N, St, BLOCK>;
     static_assert(sizeof(R) == 4, "FP32 compute: 64 elements per thread in registers");
     constexpr int TPL = C::TPL, L = C::L, NB2 = C::NB2;
     constexpr bool kUniform = L == 64;  // a wavefront is one t
@@ -925,7 +928,7 @@ __global__ void __launch_bounds__(kLanesBlock) fft_lanes(const PassArgs a) {
     const int t = t0 + h;
     {
         const cx<R> *W = reinterpret_cast<const cx<R> *>(a.tw);
-        for (int i = tid; i < N; i += kLanesBlock) tws[i] = W[i];
+        for (int i = tid; i < N; i += BLOCK) tws[i] = W[i];
         __syncthreads();
     }
     long long tile = blockIdx.x;
@@ -1470,20 +1473,20 @@ Entry make_entry(int cand) {
 }
 
 // The lane-per-line strided configuration of length N (512 or 1024).
-template <int N, class St, int DT, bool NT>
+template <int N, class St, int DT, bool NT, int BLOCK = kLanesBlock>
 Entry make_lanes_entry(int cand) {
-    using C = LanesCfg<N, St>;
+    using C = LanesCfg<N, St, BLOCK>;
     static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
     Entry e;
     e.n = N;
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NT>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NT>);
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NT, BLOCK>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NT, BLOCK>);
     e.T = C::TPL;
     e.L = C::L;
-    e.block = kLanesBlock;
+    e.block = BLOCK;
     e.lds = C::kBytes;
     e.plan = C::plan;
     return e;

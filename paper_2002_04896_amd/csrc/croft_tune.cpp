@@ -70,15 +70,18 @@ const Builtin kBuiltinForward[] = {
 };
 
 // Per-axis choices (n kind dtype axis candidate waves), looked up before
-// the two tables above: 512 strided complex64, one line per lane on both
-// axes, the z pass (2 MiB stride) with non-temporal accesses and the y pass
-// (4 KiB stride) without.
+// the two tables above, all one line per lane at 512: complex64 y (4 KiB
+// stride) in 512-thread blocks, z (2 MiB stride) in 256-thread blocks with
+// non-temporal accesses, one block per tile (two blocks share a CU); 16-bit
+// storage y in 256-thread blocks, one block per tile (z: the table above).
 struct BuiltinAxis {
     int n, kind, dtype, axis, cand, waves;
 };
 const BuiltinAxis kBuiltinAxis[] = {
     {512, 1, 0, 1, 6, 4},
-    {512, 1, 0, 2, 7, 4},
+    {512, 1, 0, 2, 9, 0},
+    {512, 1, 2, 1, 8, 0},
+    {512, 1, 3, 1, 8, 0},
 };
 
 std::mutex g_mu;
