@@ -909,7 +909,17 @@ struct LanesCfg {
     static_assert(L == 32 || L == 64, "a tile is one or two lines per wavefront lane group");
 };
 
-template <int N, class St, bool INV, bool NT, int BLOCK = kLanesBlock>
+// With one block per tile, workgroup b runs on XCD b mod 8 (the dispatcher
+// deals workgroups to the 8 XCDs in turn); this order gives each XCD one
+// contiguous run of tiles, so its L2 serves neighbouring row segments (a
+// gain for the 4 KiB stride of a 512 y pass, a loss for the z pass).
+__device__ __forceinline__ long long xcd_tile(long long b, long long n) {
+    constexpr long long kXcds = 8;
+    const long long per = n / kXcds, rem = n % kXcds, x = b % kXcds, i = b / kXcds;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
+template <int N, class St, bool INV, bool NT, int BLOCK = kLanesBlock, bool XO = false>
 __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     using R = typename St::R;
     using C = LanesCfg<N, St, BLOCK>;
@@ -934,6 +944,7 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     long long tile = blockIdx.x;
     if (tile >= a.total) return;
     const long long G = gridDim.x;
+    if (XO && G == a.total) tile = xcd_tile(tile, a.total);
     const long long es = a.es;
     long long tx = tile % a.ntiles, w = tile / a.ntiles;
     const long long gx = G % a.ntiles, gw = G / a.ntiles;
@@ -1473,7 +1484,7 @@ Entry make_entry(int cand) {
 }
 
 // The lane-per-line strided configuration of length N (512 or 1024).
-template <int N, class St, int DT, bool NT, int BLOCK = kLanesBlock>
+template <int N, class St, int DT, bool NT, int BLOCK = kLanesBlock, bool XO = false>
 Entry make_lanes_entry(int cand) {
     using C = LanesCfg<N, St, BLOCK>;
     static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
@@ -1482,8 +1493,8 @@ Entry make_lanes_entry(int cand) {
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NT, BLOCK>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NT, BLOCK>);
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NT, BLOCK, XO>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NT, BLOCK, XO>);
     e.T = C::TPL;
     e.L = C::L;
     e.block = BLOCK;

@@ -152,14 +152,14 @@ def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
 
 def test_builtin_wisdom_picks_one_line_per_lane_at_512(tmp_path, monkeypatch):
     # complex64 strided passes of length 512, both directions: one line per
-    # lane (8 threads per line) on both axes; y in 64-line tiles (512-thread
-    # blocks, persistent grid), z in 32-line tiles (256-byte rows,
-    # 256-thread blocks, one block per tile) with non-temporal accesses
+    # lane (8 threads per line) in 32-line tiles (256-byte rows, 256-thread
+    # blocks, one block per tile) on both axes, the y pass in the
+    # XCD-contiguous tile order, the z pass with non-temporal accesses
     for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
         passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64, direction)
-        assert [p["candidate"] for p in passes][1:] == ["6", "9"]
-        assert (passes[1]["T"], passes[1]["L"], passes[1]["block"], passes[1]["waves"]) == ("8", "64", "512", "4")
-        assert (passes[2]["T"], passes[2]["L"], passes[2]["block"], passes[2]["waves"]) == ("8", "32", "256", "0")
+        assert [p["candidate"] for p in passes][1:] == ["10", "9"]
+        for p in passes[1:]:
+            assert (p["T"], p["L"], p["block"], p["waves"]) == ("8", "32", "256", "0")
     # a wisdom line for any axis comes before the built-in per-axis choices
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 2 1\n", 512, 512, 512)
     assert [p["candidate"] for p in passes][1:] == ["2", "2"]
@@ -177,10 +177,10 @@ def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
 
 def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
     # complex64 at 512: the built-in choices differ between the y pass (one
-    # line per lane) and the z pass (the same in 256-thread blocks,
-    # non-temporal)
+    # line per lane, XCD-contiguous tile order) and the z pass (dispatch
+    # order)
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64)
-    assert [p["candidate"] for p in passes][1:] == ["6", "9"]
+    assert [p["candidate"] for p in passes][1:] == ["10", "9"]
     # a file line for any axis comes before the built-in per-axis choices ...
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 4 1\n", 512, 512, 512, croft.CROFT_C64)
     assert [p["candidate"] for p in passes][1:] == ["4", "4"]
@@ -192,10 +192,11 @@ def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
 
 def test_builtin_half_storage_one_line_per_lane_at_512(tmp_path, monkeypatch):
     # 16-bit storage at 512: one line per lane on both strided axes, y in
-    # 32-line tiles (256-thread blocks), z in 64-line tiles
+    # 32-line tiles (256-thread blocks, XCD-contiguous order), z in 64-line
+    # tiles
     for dt in (croft.CROFT_C16F, croft.CROFT_C16B):
         passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, dt)
-        assert [p["candidate"] for p in passes][1:] == ["8", "6"]
+        assert [p["candidate"] for p in passes][1:] == ["10", "6"]
         assert (passes[1]["T"], passes[1]["L"], passes[1]["block"]) == ("8", "32", "256")
         assert (passes[2]["T"], passes[2]["L"], passes[2]["block"]) == ("8", "64", "512")
 
