@@ -14,7 +14,8 @@ namespace dev {
 // 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
 // 5 wide tile with non-temporal loads and stores, 6 and 7 (lengths 512 and 1024) one
 // line per lane (7 non-temporal), 8 and 9 (length 512) the same in 256-thread blocks
-// (9 non-temporal), 10 and 11 those with an XCD-contiguous tile order (11 non-temporal); contiguous 3: non-temporal
+// (9 non-temporal), 10 and 11 those with an XCD-contiguous tile order (11 non-temporal);
+// at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order; contiguous 3: non-temporal
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StHalf<true>, 4, kC16B, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StHalf<true>, 4, kC16B, 0, 0, 0, 0>(2),             \
@@ -35,6 +36,7 @@ std::vector<Entry> entries_c16b() {
         make_lanes_entry<512, StHalf<true>, kC16B, false, 256>(8), make_lanes_entry<512, StHalf<true>, kC16B, true, 256>(9),
         make_lanes_entry<512, StHalf<true>, kC16B, false, 256, true>(10), make_lanes_entry<512, StHalf<true>, kC16B, true, 256, true>(11),
         make_lanes_entry<1024, StHalf<true>, kC16B, false>(6), make_lanes_entry<1024, StHalf<true>, kC16B, true>(7),
+        make_lanes_entry<1024, StHalf<true>, kC16B, false, 512, true>(8), make_lanes_entry<1024, StHalf<true>, kC16B, true, 512, true>(9),
     };
 }
 

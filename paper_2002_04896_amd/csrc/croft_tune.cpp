@@ -81,6 +81,10 @@ struct BuiltinAxis {
     int n, kind, dtype, axis, cand, waves;
 };
 const BuiltinAxis kBuiltinAxis[] = {
+    // complex64 at 1024, 512-thread blocks, one block per tile: y in the
+    // XCD-contiguous order (3.40 -> 3.29 ms), z non-temporal (4.16 -> 3.97)
+    {1024, 1, 0, 1, 8, 0},
+    {1024, 1, 0, 2, 7, 0},
     {512, 1, 0, 1, 10, 0},
     {512, 1, 0, 2, 9, 0},
     {512, 1, 2, 1, 10, 0},

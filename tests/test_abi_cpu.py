@@ -203,11 +203,13 @@ def test_builtin_half_storage_one_line_per_lane_at_512(tmp_path, monkeypatch):
 
 def test_builtin_one_line_per_lane_at_1024(tmp_path, monkeypatch):
     # complex64 strided passes of length 1024: 16 threads per line, 32-line
-    # tiles (256-byte rows) in 512-thread blocks, both axes and directions
+    # tiles (256-byte rows) in 512-thread blocks, one block per tile, both
+    # directions; y in the XCD-contiguous order, z non-temporal
     for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
         passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 1024, 1024, 1024, croft.CROFT_C64, direction)
+        assert [p["candidate"] for p in passes][1:] == ["8", "7"]
         for p in passes[1:]:
-            assert (p["candidate"], p["T"], p["L"], p["block"]) == ("7", "16", "32", "512")
+            assert (p["T"], p["L"], p["block"], p["waves"]) == ("16", "32", "512", "0")
             assert int(p["lds"]) <= 160 * 1024
 
 
