@@ -118,6 +118,18 @@ int no_kernel(int n, int dtype) {
     return fail(CROFT_ERR_UNSUPPORTED_SIZE, "no kernel for length %d", n);
 }
 
+// Non-temporal stores of part of a 128-byte line cost a read-modify-write,
+// and partial non-temporal loads fetch their lines again: where the rows of
+// a strided pass are not whole lines (a real grid's half-spectrum y pass,
+// 257 complex64 per row: 0.34-0.41 ms with the hint on loads or stores,
+// 0.20 without), a candidate with the hint gives way to its plain twin.
+void plain_on_partial_lines(const PassLaunch &p, int dtype, KernelConfig *cfg) {
+    if (p.kind != kStrided || cfg->generic || cfg->plain < 0) return;
+    if ((p.es * (long long)element_bytes(dtype)) % 128 == 0) return;
+    KernelConfig c;
+    if (select_kernel(p.n, p.kind, dtype, false, cfg->plain, &c) && c.candidate == cfg->plain) *cfg = c;
+}
+
 // Static kernels address a thread's first element as a uniform 64-bit tile
 // base plus a 32-bit per-thread byte offset; true when that offset fits.
 bool lane_offset_fits(const PassLaunch &p, int dtype) {
@@ -156,6 +168,7 @@ int build_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<P
             return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, p.kind, dtype, true, 0, &p.cfg))
             return no_kernel(n, dtype);
+        plain_on_partial_lines(p, dtype, &p.cfg);
         p.cfg.grid_waves = waves;
         if (half) {
             ExpMap &m = p.em;
@@ -232,6 +245,7 @@ int build_real_passes(const Geometry &g, int dtype, int dir, int flags, std::vec
             return no_kernel(n, dtype);
         if (!lane_offset_fits(p, dtype) && !select_kernel(n, kStrided, dtype, true, 0, &p.cfg))
             return no_kernel(n, dtype);
+        plain_on_partial_lines(p, dtype, &p.cfg);
         p.cfg.grid_waves = waves;
         yz.push_back(p);
     }
@@ -570,6 +584,10 @@ int measure_passes(croft_plan *p) {
                     PassLaunch t = *q;
                     t.cfg = cfg;
                     fits = fits && lane_offset_fits(t, p->dtype);
+                    // a candidate some pass would swap for its plain twin is not timed
+                    KernelConfig tw = cfg;
+                    plain_on_partial_lines(t, p->dtype, &tw);
+                    fits = fits && tw.candidate == cfg.candidate;
                 }
                 if (!fits) continue;
                 if ((rc = prepare_kernel(&cfg)) != CROFT_SUCCESS) break;

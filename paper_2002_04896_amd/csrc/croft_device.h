@@ -919,7 +919,8 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long n) {
     return x * per + (x < rem ? x : rem) + i;
 }
 
-template <int N, class St, bool INV, bool NT, int BLOCK = kLanesBlock, bool XO = false>
+// NTM: the non-temporal hint on the loads (bit 0) and on the stores (bit 1).
+template <int N, class St, bool INV, int NTM, int BLOCK = kLanesBlock, bool XO = false>
 __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     using R = typename St::R;
     using C = LanesCfg<N, St, BLOCK>;
@@ -979,7 +980,7 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
 #pragma unroll
             for (int m = 0; m < 64; ++m) {
                 const long long pos0 = t0 + tz + TPL * m;  // uniform part of the position
-                raw[m] = fetch_at<St, NT>(ib, pos0 * est, lane_b);
+                raw[m] = fetch_at<St, (NTM & 1) != 0>(ib, pos0 * est, lane_b);
                 if constexpr (St::kHalf)
                     ex[m] = *(const __attribute__((address_space(1))) int8_t *)(eb + ea3t * pos0 + lane_reg(elane));
             }
@@ -1070,7 +1071,7 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
                 for (int p = 0; p < TPL; ++p) {
                     // position NB2 t + u + 64 p: NB2 t0 + u + 64 p uniform, NB2 h in lane_s
                     const long long pos = (long long)NB2 * (t0 + tz) + u + 64 * p;
-                    store_at<St, NT>(ob, pos * est, lane_s, maybe_swap<INV>(y[TPL * u + p]), ex);
+                    store_at<St, (NTM & 2) != 0>(ob, pos * est, lane_s, maybe_swap<INV>(y[TPL * u + p]), ex);
                 }
             if constexpr (St::kHalf) {
                 if (t == 0 && a.out_exp) {
@@ -1459,7 +1460,15 @@ struct Entry {
     int T, L, block;
     size_t lds;
     RPlan plan;
+    int plain = -1;  // non-temporal candidates: the same kernel without the hint
 };
+
+// An entry whose kernel uses the non-temporal hint, with the candidate index
+// of its plain twin (taken where a pass's rows are not whole 128-byte lines).
+inline Entry with_plain(Entry e, int plain) {
+    e.plain = plain;
+    return e;
+}
 
 template <int N, int KIND, class St, int SB, int DT, int EPT = 0, int LREQ = 0, int PAD = 0, int PF = 1,
           int NT = 0>
@@ -1484,7 +1493,7 @@ Entry make_entry(int cand) {
 }
 
 // The lane-per-line strided configuration of length N (512 or 1024).
-template <int N, class St, int DT, bool NT, int BLOCK = kLanesBlock, bool XO = false>
+template <int N, class St, int DT, int NTM, int BLOCK = kLanesBlock, bool XO = false>
 Entry make_lanes_entry(int cand) {
     using C = LanesCfg<N, St, BLOCK>;
     static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
@@ -1493,8 +1502,8 @@ Entry make_lanes_entry(int cand) {
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NT, BLOCK, XO>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NT, BLOCK, XO>);
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO>);
     e.T = C::TPL;
     e.L = C::L;
     e.block = BLOCK;

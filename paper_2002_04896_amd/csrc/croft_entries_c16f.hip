@@ -32,11 +32,11 @@ std::vector<Entry> entries_c16f() {
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384),
         CAND(128, 16, 64, 32, 64), CAND(256, 16, 64, 32, 64), CAND(512, 16, 32, 32, 32), CAND(1024, 32, 16, 64, 16),
-        make_lanes_entry<512, StHalf<false>, kC16F, false>(6), make_lanes_entry<512, StHalf<false>, kC16F, true>(7),
-        make_lanes_entry<512, StHalf<false>, kC16F, false, 256>(8), make_lanes_entry<512, StHalf<false>, kC16F, true, 256>(9),
-        make_lanes_entry<512, StHalf<false>, kC16F, false, 256, true>(10), make_lanes_entry<512, StHalf<false>, kC16F, true, 256, true>(11),
-        make_lanes_entry<1024, StHalf<false>, kC16F, false>(6), make_lanes_entry<1024, StHalf<false>, kC16F, true>(7),
-        make_lanes_entry<1024, StHalf<false>, kC16F, false, 512, true>(8), make_lanes_entry<1024, StHalf<false>, kC16F, true, 512, true>(9),
+        make_lanes_entry<512, StHalf<false>, kC16F, 0>(6), with_plain(make_lanes_entry<512, StHalf<false>, kC16F, 3>(7), 6),
+        make_lanes_entry<512, StHalf<false>, kC16F, 0, 256>(8), with_plain(make_lanes_entry<512, StHalf<false>, kC16F, 3, 256>(9), 8),
+        make_lanes_entry<512, StHalf<false>, kC16F, 0, 256, true>(10), with_plain(make_lanes_entry<512, StHalf<false>, kC16F, 3, 256, true>(11), 10),
+        make_lanes_entry<1024, StHalf<false>, kC16F, 0>(6), with_plain(make_lanes_entry<1024, StHalf<false>, kC16F, 3>(7), 6),
+        make_lanes_entry<1024, StHalf<false>, kC16F, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StHalf<false>, kC16F, 3, 512, true>(9), 8),
     };
 }
 

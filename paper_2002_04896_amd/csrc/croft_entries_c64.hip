@@ -16,7 +16,9 @@ namespace dev {
 // 5 wide tile with non-temporal loads and stores, 6 and 7 (lengths 512 and 1024) one
 // line per lane (7 non-temporal), 8 and 9 (length 512) the same in 256-thread blocks
 // (9 non-temporal), 10 and 11 those with an XCD-contiguous tile order (11 non-temporal);
-// at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order; contiguous 3: non-temporal;
+// 12 and 13 (length 512) 8 with the non-temporal hint on the loads only and on the
+// stores only, 14 is 12 in the XCD-contiguous order; at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order; contiguous 3:
+// non-temporal;
 // fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 1, 1>(1),                 \
@@ -35,11 +37,13 @@ std::vector<Entry> entries_c64() {
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384),
         CAND(128, 16, 32, 32, 32), CAND(256, 16, 32, 32, 32), CAND(512, 16, 32, 32, 32), CAND(1024, 32, 16, 64, 16),
-        make_lanes_entry<512, StC64, kC64, false>(6), make_lanes_entry<512, StC64, kC64, true>(7),
-        make_lanes_entry<512, StC64, kC64, false, 256>(8), make_lanes_entry<512, StC64, kC64, true, 256>(9),
-        make_lanes_entry<512, StC64, kC64, false, 256, true>(10), make_lanes_entry<512, StC64, kC64, true, 256, true>(11),
-        make_lanes_entry<1024, StC64, kC64, false>(6), make_lanes_entry<1024, StC64, kC64, true>(7),
-        make_lanes_entry<1024, StC64, kC64, false, 512, true>(8), make_lanes_entry<1024, StC64, kC64, true, 512, true>(9),
+        make_lanes_entry<512, StC64, kC64, 0>(6), with_plain(make_lanes_entry<512, StC64, kC64, 3>(7), 6),
+        make_lanes_entry<512, StC64, kC64, 0, 256>(8), with_plain(make_lanes_entry<512, StC64, kC64, 3, 256>(9), 8),
+        make_lanes_entry<512, StC64, kC64, 0, 256, true>(10), with_plain(make_lanes_entry<512, StC64, kC64, 3, 256, true>(11), 10),
+        with_plain(make_lanes_entry<512, StC64, kC64, 1, 256>(12), 8), with_plain(make_lanes_entry<512, StC64, kC64, 2, 256>(13), 8),
+        with_plain(make_lanes_entry<512, StC64, kC64, 1, 256, true>(14), 10),
+        make_lanes_entry<1024, StC64, kC64, 0>(6), with_plain(make_lanes_entry<1024, StC64, kC64, 3>(7), 6),
+        make_lanes_entry<1024, StC64, kC64, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StC64, kC64, 3, 512, true>(9), 8),
     };
 }
 

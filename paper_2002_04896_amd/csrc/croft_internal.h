@@ -42,6 +42,7 @@ struct KernelConfig {
     const void *func_inv = nullptr;  // the same configuration, inverse direction
     bool generic = false;            // runtime-radix kernel
     int candidate = 0;               // index among the compiled configurations
+    int plain = -1;                  // non-temporal: the candidate without the hint
     int threads_per_line = 0;        // T
     int lines = 0;                   // L, lines per block
     int block = 0;                   // T * L

@@ -418,6 +418,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
             cfg->generic = false;
             cfg->bluestein = 0;
             cfg->candidate = pick->cand;
+            cfg->plain = pick->plain;
             cfg->threads_per_line = pick->T;
             cfg->lines = pick->L;
             cfg->block = pick->block;

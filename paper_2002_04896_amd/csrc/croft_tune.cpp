@@ -72,11 +72,11 @@ const Builtin kBuiltinForward[] = {
 // Per-axis choices (n kind dtype axis candidate waves), looked up before
 // the two tables above, all one line per lane at 512 in 256-thread blocks
 // (two share a CU), one block per tile: the y pass (4 KiB stride for
-// complex64) with the XCD-contiguous tile order and plain accesses (the
-// half-spectrum y pass of a real grid, 257 elements per row, starts its
-// tile rows off 128-byte lines, where non-temporal stores cost 0.35 against
-// 0.20 ms); the complex64 z pass (2 MiB stride) in dispatch order with
-// non-temporal accesses (16-bit z: the table above).
+// complex64) in the XCD-contiguous tile order, complex64 with non-temporal
+// loads (0.377 -> 0.363 ms; a real grid's half-spectrum y pass, whose rows
+// are not whole 128-byte lines, takes the plain twin), 16-bit storage
+// plain; the complex64 z pass (2 MiB stride) in dispatch order with
+// non-temporal loads and stores (16-bit z: the table above).
 struct BuiltinAxis {
     int n, kind, dtype, axis, cand, waves;
 };
@@ -92,7 +92,7 @@ const BuiltinAxis kBuiltinAxis[] = {
     {1024, 1, 2, 2, 9, 0},
     {1024, 1, 3, 1, 6, 1},
     {1024, 1, 3, 2, 9, 0},
-    {512, 1, 0, 1, 10, 0},
+    {512, 1, 0, 1, 14, 0},
     {512, 1, 0, 2, 9, 0},
     {512, 1, 2, 1, 10, 0},
     {512, 1, 3, 1, 10, 0},
