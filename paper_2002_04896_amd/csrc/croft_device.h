@@ -920,7 +920,9 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long n) {
 }
 
 // NTM: the non-temporal hint on the loads (bit 0) and on the stores (bit 1).
-template <int N, class St, bool INV, int NTM, int BLOCK = kLanesBlock, bool XO = false>
+// REV: with one block per tile, the tiles in reverse order (the pass starts
+// where the previous pass, run forward, stopped writing).
+template <int N, class St, bool INV, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false>
 __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     using R = typename St::R;
     using C = LanesCfg<N, St, BLOCK>;
@@ -946,6 +948,7 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     if (tile >= a.total) return;
     const long long G = gridDim.x;
     if (XO && G == a.total) tile = xcd_tile(tile, a.total);
+    if (REV && G == a.total) tile = a.total - 1 - tile;
     const long long es = a.es;
     long long tx = tile % a.ntiles, w = tile / a.ntiles;
     const long long gx = G % a.ntiles, gw = G / a.ntiles;
@@ -1460,11 +1463,13 @@ struct Entry {
     int T, L, block;
     size_t lds;
     RPlan plan;
-    int plain = -1;  // non-temporal candidates: the same kernel without the hint
+    int plain = -1;  // non-temporal candidates: the candidate without the hint
 };
 
 // An entry whose kernel uses the non-temporal hint, with the candidate index
-// of its plain twin (taken where a pass's rows are not whole 128-byte lines).
+// of its plain twin, taken where a pass's rows are not whole 128-byte lines:
+// the same kernel without the hint, or, where another plain kernel is the
+// faster one there, that one.
 inline Entry with_plain(Entry e, int plain) {
     e.plain = plain;
     return e;
@@ -1493,7 +1498,7 @@ Entry make_entry(int cand) {
 }
 
 // The lane-per-line strided configuration of length N (512 or 1024).
-template <int N, class St, int DT, int NTM, int BLOCK = kLanesBlock, bool XO = false>
+template <int N, class St, int DT, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false>
 Entry make_lanes_entry(int cand) {
     using C = LanesCfg<N, St, BLOCK>;
     static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
@@ -1502,8 +1507,8 @@ Entry make_lanes_entry(int cand) {
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO>);
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO, REV>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO, REV>);
     e.T = C::TPL;
     e.L = C::L;
     e.block = BLOCK;

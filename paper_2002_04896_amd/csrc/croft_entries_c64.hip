@@ -17,7 +17,8 @@ namespace dev {
 // line per lane (7 non-temporal), 8 and 9 (length 512) the same in 256-thread blocks
 // (9 non-temporal), 10 and 11 those with an XCD-contiguous tile order (11 non-temporal);
 // 12 and 13 (length 512) 8 with the non-temporal hint on the loads only and on the
-// stores only, 14 is 12 in the XCD-contiguous order; at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order; contiguous 3:
+// stores only, 14 is 12 in the XCD-contiguous order, 15 and 16 are 12 and 8 with the
+// tiles in reverse order; at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order; contiguous 3:
 // non-temporal;
 // fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
 #define CAND(N, EW, LW, EW2, LW2)                                                \
@@ -42,6 +43,8 @@ std::vector<Entry> entries_c64() {
         make_lanes_entry<512, StC64, kC64, 0, 256, true>(10), with_plain(make_lanes_entry<512, StC64, kC64, 3, 256, true>(11), 10),
         with_plain(make_lanes_entry<512, StC64, kC64, 1, 256>(12), 8), with_plain(make_lanes_entry<512, StC64, kC64, 2, 256>(13), 8),
         with_plain(make_lanes_entry<512, StC64, kC64, 1, 256, true>(14), 10),
+        with_plain(make_lanes_entry<512, StC64, kC64, 1, 256, false, true>(15), 10),
+        make_lanes_entry<512, StC64, kC64, 0, 256, false, true>(16),
         make_lanes_entry<1024, StC64, kC64, 0>(6), with_plain(make_lanes_entry<1024, StC64, kC64, 3>(7), 6),
         make_lanes_entry<1024, StC64, kC64, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StC64, kC64, 3, 512, true>(9), 8),
     };

@@ -72,10 +72,11 @@ const Builtin kBuiltinForward[] = {
 // Per-axis choices (n kind dtype axis candidate waves), looked up before
 // the two tables above, all one line per lane at 512 in 256-thread blocks
 // (two share a CU), one block per tile: the y pass (4 KiB stride for
-// complex64) in the XCD-contiguous tile order with non-temporal loads
-// (complex64 0.377 -> 0.363 ms, FP16 0.230 -> 0.213 ms; a real grid's
-// half-spectrum y pass, whose rows are not whole 128-byte lines, takes the
-// plain twin); the complex64 z pass (2 MiB stride) in dispatch order with
+// complex64) with non-temporal loads, complex64 with the tiles in reverse
+// order (0.377 -> 0.350 ms), 16-bit storage in the XCD-contiguous order
+// (0.230 -> 0.213 ms); a real grid's half-spectrum y pass, whose rows are
+// not whole 128-byte lines, takes the plain twin (the XCD-ordered plain
+// kernel, 0.20 ms); the complex64 z pass (2 MiB stride) in dispatch order with
 // non-temporal loads and stores (16-bit z: the table above).
 struct BuiltinAxis {
     int n, kind, dtype, axis, cand, waves;
@@ -92,7 +93,7 @@ const BuiltinAxis kBuiltinAxis[] = {
     {1024, 1, 2, 2, 9, 0},
     {1024, 1, 3, 1, 6, 1},
     {1024, 1, 3, 2, 9, 0},
-    {512, 1, 0, 1, 14, 0},
+    {512, 1, 0, 1, 15, 0},
     {512, 1, 0, 2, 9, 0},
     {512, 1, 2, 1, 14, 0},
     {512, 1, 3, 1, 14, 0},

@@ -153,12 +153,12 @@ def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
 def test_builtin_wisdom_picks_one_line_per_lane_at_512(tmp_path, monkeypatch):
     # complex64 strided passes of length 512, both directions: one line per
     # lane (8 threads per line) in 32-line tiles (256-byte rows, 256-thread
-    # blocks, one block per tile) on both axes, the y pass in the
-    # XCD-contiguous tile order with non-temporal loads, the z pass with
-    # non-temporal loads and stores
+    # blocks, one block per tile) on both axes, the y pass with non-temporal
+    # loads and the tiles in reverse order, the z pass with non-temporal
+    # loads and stores
     for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
         passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64, direction)
-        assert [p["candidate"] for p in passes][1:] == ["14", "9"]
+        assert [p["candidate"] for p in passes][1:] == ["15", "9"]
         for p in passes[1:]:
             assert (p["T"], p["L"], p["block"], p["waves"]) == ("8", "32", "256", "0")
     # a wisdom line for any axis comes before the built-in per-axis choices
@@ -178,14 +178,14 @@ def test_wisdom_file_overrides_choice(tmp_path, monkeypatch):
 
 def test_non_temporal_candidates_give_way_on_partial_lines(tmp_path, monkeypatch):
     # a real grid's half-spectrum y pass has 257 complex64 per row, not whole
-    # 128-byte lines: the complex grid's y choice (candidate 14, non-temporal
+    # 128-byte lines: the complex grid's y choice (candidate 15, non-temporal
     # loads) gives way to its plain twin (10); the z rows (257 * 512
     # elements) are whole lines and keep the non-temporal candidate 9
     monkeypatch.setenv("CROFT_WISDOM", str(tmp_path / "none.txt"))
     passes = parse_describe(croft.croft_plan_describe_real(512, 512, 512))[1]
     assert [p["candidate"] for p in passes][1:] == ["10", "9"]
     # the same twin for any non-temporal candidate named in a wisdom file
-    for cand, plain in ((7, 6), (9, 8), (11, 10), (12, 8), (13, 8), (14, 10)):
+    for cand, plain in ((7, 6), (9, 8), (11, 10), (12, 8), (13, 8), (14, 10), (15, 10)):
         w = tmp_path / "w.txt"
         w.write_text(f"512 1 0 {cand} 0 1\n")
         monkeypatch.setenv("CROFT_WISDOM", str(w))
@@ -200,7 +200,7 @@ def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
     # line per lane, XCD-contiguous tile order) and the z pass (dispatch
     # order)
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64)
-    assert [p["candidate"] for p in passes][1:] == ["14", "9"]
+    assert [p["candidate"] for p in passes][1:] == ["15", "9"]
     # a file line for any axis comes before the built-in per-axis choices ...
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 4 1\n", 512, 512, 512, croft.CROFT_C64)
     assert [p["candidate"] for p in passes][1:] == ["4", "4"]
