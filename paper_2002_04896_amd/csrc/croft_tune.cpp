@@ -70,14 +70,14 @@ const Builtin kBuiltinForward[] = {
 };
 
 // Per-axis choices (n kind dtype axis candidate waves), looked up before
-// the two tables above, all one line per lane at 512 in 256-thread blocks
-// (two share a CU), one block per tile: the y pass (4 KiB stride for
-// complex64) with non-temporal loads, complex64 with the tiles in reverse
-// order (0.377 -> 0.350 ms), 16-bit storage in the XCD-contiguous order
-// (0.230 -> 0.213 ms); a real grid's half-spectrum y pass, whose rows are
-// not whole 128-byte lines, takes the plain twin (the XCD-ordered plain
-// kernel, 0.20 ms); the complex64 z pass (2 MiB stride) in dispatch order with
-// non-temporal loads and stores (16-bit z: the table above).
+// the two tables above, all one line per lane; at 512 in 256-thread blocks
+// (two share a CU), one block per tile, unless noted: the y pass (4 KiB
+// stride for complex64) with non-temporal loads, complex64 with the tiles
+// in reverse order (0.377 -> 0.350 ms), 16-bit storage in the
+// XCD-contiguous order (0.230 -> 0.213 ms); a real grid's half-spectrum y
+// pass, whose rows are not whole 128-byte lines, takes the plain twin (the
+// XCD-ordered plain kernel, 0.20 ms); the complex64 z pass (2 MiB stride)
+// in dispatch order with non-temporal loads and stores.
 struct BuiltinAxis {
     int n, kind, dtype, axis, cand, waves;
 };
@@ -97,6 +97,10 @@ const BuiltinAxis kBuiltinAxis[] = {
     {512, 1, 0, 2, 9, 0},
     {512, 1, 2, 1, 14, 0},
     {512, 1, 3, 1, 14, 0},
+    // 16-bit storage z at 512: 64-line tiles with non-temporal stores
+    // (0.755 -> 0.738 ms per transform, both directions)
+    {512, 1, 2, 2, 16, 1},
+    {512, 1, 3, 2, 16, 1},
 };
 
 std::mutex g_mu;
