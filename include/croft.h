@@ -109,8 +109,13 @@ croft_plan_t croft_plan_create(int nx, int ny, int nz, int dtype, int dir);
  * x pass is read back by the y pass while still cache resident; the z pass
  * then runs over the whole grid.  This is the one-GPU form of the paper's
  * overlap of chunked communication with computation and its iteration
- * parameter K (Section 5.1).  K must divide nz; K = 0 lets the plan choose,
- * K = 1 is the plain three-pass schedule.  The result does not depend on K. */
+ * parameter K (Section 5.1, where K = 2).  K must divide nz; K = 1 is the
+ * plain three-pass schedule.  K = 0 lets the plan choose: with CROFT_MEASURE
+ * it times the whole transform for every K in {1, 2, 4, 8, 16} dividing nz,
+ * keeps the fastest and records it in the wisdom (the CROFT_WISDOM file as
+ * "slabs nx ny nz dtype K", and this process); without CROFT_MEASURE it
+ * takes a recorded K for the same grid and dtype, else 1.  The chosen K is
+ * croft_plan_info.slabs.  The result does not depend on K (bit for bit). */
 croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, int flags, int slabs);
 
 /* Run the transform of a C64/C128 plan.  in == out runs in place; otherwise

@@ -58,7 +58,9 @@ struct croft_plan {
     // convolution plans (real, with the fused multiply pass): energy partials
     bool conv = false;
     double *partial = nullptr;
-    // slab schedule
+    long long partial_count = 0;  // doubles in `partial`
+    // slab schedule; slab_auto: K was left to the plan (K = 0 at create)
+    bool slab_auto = false;
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
     // batched form: one launch per pass over the grids the batched kernel
@@ -137,6 +139,20 @@ bool lane_offset_fits(const PassLaunch &p, int dtype) {
     const long long L = p.cfg.lines, T = p.cfg.threads_per_line;
     const long long e = strided_kind(p.kind) ? (L - 1) + (T - 1) * p.es : (L - 1) * p.n + (T - 1);
     return (e + 1) * (long long)element_bytes(dtype) <= 0xffffffffLL;
+}
+
+// Most blocks a fused multiply pass can launch, over every compiled
+// configuration of its length (the autotuner launches each of them, and the
+// wisdom may pick any) and the runtime-radix one: one energy partial per
+// block.  A persistent grid launches at most its tile count.
+long long conv_partials_needed(const PassLaunch &pl, int dtype) {
+    long long most = pass_tiles(pl);
+    PassLaunch t = pl;
+    const int ncand = kernel_candidates(pl.n, kConvZ, dtype);
+    for (int c = 0; c < ncand; ++c)
+        if (select_kernel(pl.n, kConvZ, dtype, false, c, &t.cfg)) most = std::max(most, pass_tiles(t));
+    if (select_generic_conv(pl.n, dtype, &t.cfg)) most = std::max(most, pass_tiles(t));
+    return std::max(1LL, most);
 }
 
 // The pass list of one grid, without device resources (twiddle pointers are
@@ -483,14 +499,15 @@ int attach_resources(croft_plan *p) {
         }
     }
     if (p->conv) {
-        long long tiles = 0;
+        long long count = 1;
         for (const PassLaunch &pl : p->passes[0])
-            if (pl.kind == kConvZ) tiles = pass_tiles(pl);  // most blocks any grid size launches
-        if ((e = hipMalloc((void **)&p->partial, sizeof(double) * (size_t)std::max(1LL, tiles))) != hipSuccess) {
+            if (pl.kind == kConvZ) count = std::max(count, conv_partials_needed(pl, p->dtype));
+        if ((e = hipMalloc((void **)&p->partial, sizeof(double) * (size_t)count)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "energy partials: %s", hipGetErrorString(e));
         }
-        p->work_bytes += sizeof(double) * (size_t)std::max(1LL, tiles);
+        p->partial_count = count;
+        p->work_bytes += sizeof(double) * (size_t)count;
     }
     if (p->real && (p->dir == CROFT_BACKWARD || p->conv) && p->passes[0].size() > 1) {
         const Geometry &g = p->grids[0];
@@ -510,7 +527,7 @@ int attach_resources(croft_plan *p) {
         }
         p->work_bytes += b1 + b2;
     }
-    if (p->slabs > 1) {
+    if (p->slabs > 1 || (p->slab_auto && (p->flags & CROFT_MEASURE))) {
         for (int i = 0; i < 2; ++i) {
             if ((e = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking)) != hipSuccess)
                 return fail_hip(e, "stream create");
@@ -601,6 +618,11 @@ int measure_passes(croft_plan *p) {
                         PassLaunch t = *q;
                         t.cfg = cfg;
                         t.cfg.grid_waves = waves;
+                        if (t.kind == kConvZ && pass_blocks(t) > p->partial_count) {
+                            rc = fail(CROFT_ERR_INTERNAL, "fused pass of %lld blocks exceeds %lld energy partials",
+                                      pass_blocks(t), p->partial_count);
+                            break;
+                        }
                         for (int d = 0; d < ndir && e == hipSuccess; ++d) {
                             const int iv = ndir == 2 ? d : (int)inv;
                             float best_rep = 1e30f;
@@ -618,6 +640,7 @@ int measure_passes(croft_plan *p) {
                         }
                         if (e != hipSuccess) break;
                     }
+                    if (rc != CROFT_SUCCESS) break;
                     if (e != hipSuccess) {
                         rc = fail_hip(e, "autotune launch");
                         break;
@@ -641,6 +664,85 @@ int measure_passes(croft_plan *p) {
             auto it = best.find({pl.n, pl.kind, wisdom_axis(pl.kind, pl.axis)});
             if (it != best.end()) pl.cfg = it->second;
         }
+    return CROFT_SUCCESS;
+}
+
+int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp,
+             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof);
+int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp, hipStream_t s,
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof);
+
+// The slab counts a grid can take: 1, 2, 4, 8, 16 where they divide nz.
+std::vector<int> slab_candidates(int nz) {
+    std::vector<int> ks;
+    for (int k : {1, 2, 4, 8, 16})
+        if (nz % k == 0) ks.push_back(k);
+    return ks;
+}
+
+// CROFT_MEASURE with K = 0: time the whole transform (the plan's direction,
+// its chosen pass configurations) under each slab count on scratch buffers,
+// keep the fastest (best of five runs each) and record it as wisdom.
+int measure_slabs(croft_plan *p) {
+    const Geometry &g = p->grids[0];
+    const std::vector<int> ks = slab_candidates(g.nz);
+    const size_t bytes = (size_t)g.nx * g.ny * g.nz * element_bytes(p->dtype);
+    const size_t ebytes = std::max((size_t)g.ny * g.nz, (size_t)g.nx * g.ny);
+    void *a = nullptr, *b = nullptr;
+    int8_t *ei = nullptr, *eo = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    auto cleanup = [&]() {
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (ei) (void)hipFree(ei);
+        if (eo) (void)hipFree(eo);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    };
+    if (ks.size() > 1) {
+        if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess ||
+            hipMalloc((void **)&ei, ebytes) != hipSuccess || hipMalloc((void **)&eo, ebytes) != hipSuccess) {
+            (void)hipGetLastError();
+            cleanup();
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "slab autotune scratch of %zu bytes", 2 * bytes);
+        }
+        hipError_t e;
+        if ((e = hipMemset(a, 0, bytes)) != hipSuccess || (e = hipMemset(ei, 0, ebytes)) != hipSuccess ||
+            (e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+            cleanup();
+            return fail_hip(e, "slab autotune setup");
+        }
+    }
+    int best_k = 1;
+    float best_ms = 1e30f;
+    int rc = CROFT_SUCCESS;
+    for (size_t i = 0; i < ks.size() && ks.size() > 1 && rc == CROFT_SUCCESS; ++i) {
+        p->slabs = ks[i];
+        auto once = [&]() {
+            return ks[i] > 1 ? run_slabs(p, (const char *)a, (char *)b, ei, eo, nullptr, nullptr)
+                             : run_grid(p, 0, (const char *)a, (char *)b, ei, eo, nullptr, nullptr);
+        };
+        if ((rc = once()) != CROFT_SUCCESS) break;  // warm-up
+        float best_rep = 1e30f;
+        for (int rep = 0; rep < 5 && rc == CROFT_SUCCESS; ++rep) {
+            float ms = 0.f;
+            hipError_t e = hipEventRecord(t0, nullptr);
+            if (e == hipSuccess && (rc = once()) != CROFT_SUCCESS) break;
+            if (e == hipSuccess) e = hipEventRecord(t1, nullptr);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e != hipSuccess) rc = fail_hip(e, "slab autotune timing");
+            best_rep = std::min(best_rep, ms);
+        }
+        if (best_rep < best_ms) {
+            best_ms = best_rep;
+            best_k = ks[i];
+        }
+    }
+    cleanup();
+    if (rc != CROFT_SUCCESS) return rc;
+    p->slabs = best_k;
+    slab_wisdom_record(g.nx, g.ny, g.nz, p->dtype, best_k, !(p->flags & CROFT_NO_WISDOM));
     return CROFT_SUCCESS;
 }
 
@@ -751,7 +853,15 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
         return nullptr;
     }
     p->batched = batched;
+    if (slabs == 0) {
+        // K left to the plan: a recorded choice for this grid, else 1;
+        // CROFT_MEASURE times every K below
+        p->slab_auto = true;
+        int k = 1;
+        p->slabs = slab_wisdom_lookup(grids[0].nx, grids[0].ny, grids[0].nz, dtype, &k) ? k : 1;
+    }
     if (attach_resources(p) != CROFT_SUCCESS || ((flags & CROFT_MEASURE) && measure_passes(p) != CROFT_SUCCESS) ||
+        (p->slab_auto && (flags & CROFT_MEASURE) && measure_slabs(p) != CROFT_SUCCESS) ||
         (p->batched && build_batch_tables(p) != CROFT_SUCCESS)) {
         std::string msg = g_last_error;
         destroy_plan(p);
@@ -783,6 +893,9 @@ int run_pass(croft_plan *p, const PassLaunch &pl, const void *in, void *out, con
         if (!a || !b) return fail(CROFT_ERR_HIP, "profiling event creation failed");
         (void)hipEventRecord(a, s);
     }
+    if (pl.kind == kConvZ && pass_blocks(pl) > p->partial_count)
+        return fail(CROFT_ERR_INTERNAL, "fused pass of %lld blocks exceeds %lld energy partials", pass_blocks(pl),
+                    p->partial_count);
     const int dir = pl.dir ? pl.dir : p->dir;
     const hipError_t e = launch_pass(pl, p->dtype, in, out, ie, oe, dir == CROFT_BACKWARD, s, mul, p->partial);
     if (e != hipSuccess) return fail_hip(e, "kernel launch");
@@ -1040,6 +1153,13 @@ int describe_impl(int nx, int ny, int nz, int dtype, int dir, int mode, char *bu
                  pl.cfg.block, blocks, pl.cfg.lds, pl.cfg.candidate, pl.cfg.grid_waves, pl.cfg.bluestein);
         s += line;
     }
+    if (mode == 2) {
+        long long count = 1;
+        for (const PassLaunch &pl : ps)
+            if (pl.kind == kConvZ) count = std::max(count, conv_partials_needed(pl, dtype));
+        snprintf(line, sizeof line, "energy_partials=%lld\n", count);
+        s += line;
+    }
     if (len) {
         const size_t n = std::min(len - 1, s.size());
         std::memcpy(buf, s.data(), n);
@@ -1067,7 +1187,6 @@ croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, in
         fail(CROFT_ERR_INVALID_VALUE, "slab count %d must be 0, 1 or a divisor of nz = %d", slabs, nz);
         return nullptr;
     }
-    if (slabs == 0) slabs = 1;
     return new_plan({Geometry{nx, ny, nz}}, dtype, dir, flags, slabs);
 }
 

@@ -161,6 +161,9 @@ hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t l
 // for the other kinds.
 bool wisdom_lookup(int n, int kind, int dtype, int dir, int axis, int *cand, int *waves);
 void wisdom_record(int n, int kind, int dtype, int axis, int cand, int waves, bool persist);
+// Slab count K of the pipelined schedule for a grid and dtype (K divides nz).
+bool slab_wisdom_lookup(int nx, int ny, int nz, int dtype, int *k);
+void slab_wisdom_record(int nx, int ny, int nz, int dtype, int k, bool persist);
 // The axis a pass's wisdom is keyed on.
 inline int wisdom_axis(int kind, int axis) { return kind == kStrided ? axis : -1; }
 

@@ -6,6 +6,7 @@
 // this process are kept in memory; when the environment variable CROFT_WISDOM
 // names a file, plans also read it and CROFT_MEASURE plans append to it.
 // File format, one choice per line:  n kind dtype candidate waves [axis]
+// (and "slabs nx ny nz dtype K" for the slab count of a grid, below)
 // A strided pass also has a choice of its own per grid axis (1 = y, 2 = z:
 // their strides differ, and so can their best tiles); a line without an axis
 // serves every axis.  Lookup order: the CROFT_WISDOM file, choices measured
@@ -179,6 +180,55 @@ void wisdom_record(int n, int kind, int dtype, int axis, int cand, int waves, bo
     if (FILE *f = std::fopen(path, "a")) {
         if (axis >= 0) std::fprintf(f, "%d %d %d %d %d %d\n", n, kind, dtype, cand, waves, axis);
         else std::fprintf(f, "%d %d %d %d %d\n", n, kind, dtype, cand, waves);
+        std::fclose(f);
+    }
+}
+
+// ---- slab count K of the pipelined schedule ----
+// File lines "slabs nx ny nz dtype K"; the same lookup order as the pass
+// choices (file, this process, built-in).  No built-in grid takes K > 1: on
+// an MI355X the measured gain of the slab schedule at 512^3 and 1024^3 is
+// within the spread of repeated runs.
+namespace {
+std::map<std::tuple<int, int, int, int>, int> g_slabs;  // (nx, ny, nz, dtype) -> K
+
+bool read_slabs(const char *path, int nx, int ny, int nz, int dtype, int *k) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    int a, b, c, d, e;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "slabs %d %d %d %d %d", &a, &b, &c, &d, &e) != 5) continue;
+        if (a == nx && b == ny && c == nz && d == dtype && e >= 1 && nz % e == 0) {
+            *k = e;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+}  // namespace
+
+bool slab_wisdom_lookup(int nx, int ny, int nz, int dtype, int *k) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const char *path = std::getenv("CROFT_WISDOM");
+    if (path && *path && read_slabs(path, nx, ny, nz, dtype, k)) return true;
+    auto it = g_slabs.find({nx, ny, nz, dtype});
+    if (it != g_slabs.end()) {
+        *k = it->second;
+        return true;
+    }
+    return false;
+}
+
+void slab_wisdom_record(int nx, int ny, int nz, int dtype, int k, bool persist) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_slabs[{nx, ny, nz, dtype}] = k;
+    const char *path = std::getenv("CROFT_WISDOM");
+    if (!persist || !path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "slabs %d %d %d %d %d\n", nx, ny, nz, dtype, k);
         std::fclose(f);
     }
 }

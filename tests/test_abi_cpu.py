@@ -91,9 +91,19 @@ def parse_describe(text):
     head = lines[0]
     passes = []
     for ln in lines[1:]:
+        if not ln.startswith("pass "):
+            continue
         kv = dict(tok.split("=", 1) for tok in ln.split()[2:])
         passes.append(kv)
     return head, passes
+
+
+def describe_extra(text, key):
+    """The value of a `key=value` line of a dry-run description."""
+    for ln in text.strip().split("\n"):
+        if ln.startswith(key + "="):
+            return ln.split("=", 1)[1]
+    raise KeyError(key)
 
 
 def test_describe_512_cube():
@@ -347,3 +357,28 @@ def test_describe_convolution_uncompiled_fused_length_runs_the_runtime_kernel():
     assert passes[2]["kind"] == "fused" and passes[2]["kernel"] == "generic"
     _, passes = parse_describe(croft.croft_plan_describe_convolution(32, 20, 64))
     assert passes[2]["kind"] == "fused" and passes[2]["kernel"] == "static"
+
+
+@pytest.mark.parametrize("dims,dt,n", [((512, 512, 256), croft.CROFT_C64, 256),
+                                       ((512, 64, 512), croft.CROFT_C64, 512),
+                                       ((64, 64, 128), croft.CROFT_C128, 128)])
+def test_energy_partials_cover_every_fused_candidate(dims, dt, n, tmp_path, monkeypatch):
+    """The convolution plan holds one energy partial per block of its fused
+    pass; the autotuner launches every compiled candidate of the fused length
+    (they differ in lines per tile, so in block count), and the wisdom may
+    start the plan on any of them.  Whatever candidate the plan starts on,
+    the partials it sizes must cover the largest block count among them."""
+    w = tmp_path / "w.txt"
+    monkeypatch.setenv("CROFT_WISDOM", str(w))
+    counts, blocks = set(), []
+    for cand in range(4):
+        for waves in (0, 1, 2):
+            w.write_text(f"{n} 3 {dt} {cand} {waves}\n")
+            text = croft.croft_plan_describe_convolution(*dims, dt)
+            fused = [p for p in parse_describe(text)[1] if p["kind"] == "fused"]
+            assert len(fused) == 1
+            blocks.append(int(fused[0]["blocks"]))
+            counts.add(int(describe_extra(text, "energy_partials")))
+    assert len(counts) == 1, counts                       # independent of the starting candidate
+    assert len(set(blocks)) > 1                            # the candidates do differ in block count
+    assert counts.pop() >= max(blocks)

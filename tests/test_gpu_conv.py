@@ -103,6 +103,35 @@ def test_measure_flag_gives_the_same_bits(dtype):
     assert ea == eb
 
 
+def test_measure_from_a_wide_tile_start_stays_within_the_energy_partials(tmp_path, monkeypatch):
+    """A fused length of 256 has two compiled candidates of different lines
+    per tile (complex64: 16 and 32), so their block counts differ.  Seeded
+    with the wider tile (fewer blocks), the plan's partials must still hold
+    every block of the narrower one, which the autotuner launches; run twice,
+    the second plan starting from the first one's recorded choice."""
+    w = tmp_path / "w.txt"
+    w.write_text("256 3 0 1 0\n")
+    monkeypatch.setenv("CROFT_WISDOM", str(w))
+    dims = (64, 32, 256)
+    nx, ny, nz = dims
+    x = synth.normal_c((nz, ny, nx), seed=35).real.astype(np.float32)
+    g = synth.pme_influence(nx, ny, nz)
+    ref, ref_e = oracle.convolve_real(x.astype(np.float64), g.astype(np.float32).astype(np.float64))
+    outs = []
+    for rep in range(2):
+        got, energy = run_conv(x, g, C64, flags=croft.CROFT_MEASURE)
+        assert oracle.rel_l2(got, ref) <= TOL[C64], rep
+        assert abs(energy - ref_e) <= 1e-5 * abs(ref_e), rep
+        outs.append((got, energy))
+    plain, plain_e = run_conv(x, g, C64)
+    for got, energy in outs:
+        # the butterflies are the same in every candidate; the energy's
+        # per-block partials follow the tile partition, so only its rounding
+        # may differ
+        np.testing.assert_array_equal(got, plain)
+        assert abs(energy - plain_e) <= 1e-12 * abs(plain_e)
+
+
 def unfused(d_x, d_g, dtype):
     """The same steps as separate plans: real forward, multiply, real backward."""
     nz, ny, nx = d_x.shape

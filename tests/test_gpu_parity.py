@@ -377,3 +377,80 @@ def test_batched_in_place():
     np.testing.assert_array_equal(outs[0], outs[1])
     seen = flat[:64 * 48 * 60].reshape(60, 48, 64).astype(np.complex128)
     assert oracle.rel_l2(outs[0][:64 * 48 * 60].reshape(60, 48, 64), oracle.dft3d(seen)) <= TOL[C64]
+
+
+# ------------------------------------------------ slab schedule (paper Section 5.1, K)
+# (nz, ny, nx): non-cubic grids whose slabs split z into 2, 4 and 8; ragged
+# tiles along x and y, and runtime-radix passes (30 and 100)
+SLAB_SHAPES = [(64, 40, 48), (16, 30, 100)]
+
+
+@pytest.mark.parametrize("shape", SLAB_SHAPES, ids=str)
+@pytest.mark.parametrize("slabs", [2, 4, 8])
+@pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
+def test_slab_schedule_against_oracle_c64(shape, slabs, direction):
+    """K > 1 against the FP64 oracle, not only against the plain schedule."""
+    x = synth.normal_c(shape, seed=60 + slabs)
+    seen, y, after = run_fft(x, C64, direction, slabs=slabs)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, direction)) <= TOL[C64]
+    assert np.array_equal(after, seen)
+    _, plain, _ = run_fft(x, C64, direction)
+    assert np.array_equal(y, plain)
+
+
+@pytest.mark.parametrize("slabs", [2, 4, 8])
+@pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
+def test_slab_schedule_against_oracle_c128(slabs, direction):
+    x = synth.normal_c((32, 24, 20), seed=70 + slabs)
+    seen, y, _ = run_fft(x, C128, direction, slabs=slabs)
+    assert oracle.rel_l2(y, oracle.dft3d(seen, direction)) <= TOL[C128]
+
+
+@pytest.mark.parametrize("shape", SLAB_SHAPES, ids=str)
+@pytest.mark.parametrize("slabs", [2, 4, 8])
+@pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
+@pytest.mark.parametrize("dtype", [F16, BF16], ids=["f16", "bf16"])
+def test_slab_schedule_against_oracle_half(shape, slabs, direction, dtype):
+    kind = HALF_KIND[dtype]
+    v = synth.normal_c(shape, seed=80 + slabs)
+    data, e = synth.quantize_half(v, kind)
+    exact_in = oracle.decode_half(data, e, kind, 0)
+    out, oe = run_half(data, e, dtype, direction, slabs=slabs)
+    got = oracle.decode_half(out, oe, kind, 2)
+    assert oracle.rel_l2(got, oracle.dft3d(exact_in, direction)) <= TOL[dtype]
+    check_half_output(out, oe, kind)
+    ref_out, ref_e = run_half(data, e, dtype, direction)
+    assert np.array_equal(out, ref_out) and np.array_equal(oe, ref_e)
+
+
+@pytest.mark.parametrize("dtype", [C64, F16], ids=["c64", "f16"])
+def test_slab_count_zero_is_chosen_by_measurement_and_recorded(dtype, tmp_path, monkeypatch):
+    """K = 0 with CROFT_MEASURE times K in {1, 2, 4, 8, 16} dividing nz and
+    records the pick; a later K = 0 plan of the same grid and dtype without
+    CROFT_MEASURE takes it; an explicit K is kept as given."""
+    wisdom = tmp_path / "w.txt"
+    monkeypatch.setenv("CROFT_WISDOM", str(wisdom))
+    nz, ny, nx = 48, 40, 64
+    plan = croft.croft_plan_create_ex(nx, ny, nz, dtype, FWD, croft.CROFT_MEASURE, 0)
+    k = croft.croft_plan_info(plan)["slabs"]
+    croft.croft_plan_destroy(plan)
+    assert k in (1, 2, 4, 8, 16) and nz % k == 0
+    recorded = [l.split() for l in wisdom.read_text().splitlines() if l.startswith("slabs")]
+    assert recorded and recorded[-1] == ["slabs", str(nx), str(ny), str(nz), str(dtype), str(k)]
+    # a recorded K is taken by a K = 0 plan; a K named in the file wins
+    wisdom.write_text(wisdom.read_text() + f"slabs {nx} {ny} {nz} {dtype} 16\n")
+    plan = croft.croft_plan_create_ex(nx, ny, nz, dtype, FWD, 0, 0)
+    assert croft.croft_plan_info(plan)["slabs"] == 16
+    croft.croft_plan_destroy(plan)
+    plan = croft.croft_plan_create_ex(nx, ny, nz, dtype, FWD, 0, 4)
+    assert croft.croft_plan_info(plan)["slabs"] == 4
+    croft.croft_plan_destroy(plan)
+    # with nothing recorded for a grid, K = 0 is the plain schedule
+    plan = croft.croft_plan_create_ex(nx, ny, 7, dtype, FWD, 0, 0)
+    assert croft.croft_plan_info(plan)["slabs"] == 1
+    croft.croft_plan_destroy(plan)
+    # the chosen K runs and matches the oracle
+    if dtype == C64:
+        x = synth.normal_c((nz, ny, nx), seed=90)
+        seen, y, _ = run_fft(x, C64, FWD, slabs=0)
+        assert oracle.rel_l2(y, oracle.dft3d(seen, FWD)) <= TOL[C64]
