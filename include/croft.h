@@ -135,6 +135,27 @@ int croft_execute(croft_plan_t plan, const void *in, void *out, hipStream_t stre
 int croft_execute_scaled(croft_plan_t plan, const void *in, const int8_t *in_exp, void *out,
                          int8_t *out_exp, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as croft_execute_scaled, with the same arguments and results bit
+ * for bit, but the intermediate per-line exponents (ny*nz bytes after the x
+ * pass, nx*nz after the y pass) live in a static array of
+ * CROFT_NOALLOC_SCRATCH_BYTES on each GPU instead of the plan's own, and the
+ * call allocates nothing (no device or host allocation, no event or stream
+ * creation).  Every call on a GPU shares that GPU's array, which keeps the
+ * last call's contents (each pass writes all the exponents the next one
+ * reads, so nothing needs clearing): calls that overlap on one GPU, from any
+ * plans or streams, race -- order them on one stream.  The array is
+ * allocated when the library is loaded and held by each GPU until the
+ * process ends.
+ * Errors: CROFT_ERR_UNSUPPORTED_SIZE when ny*nz (rounded up to 256) plus
+ * nx*nz exceeds CROFT_NOALLOC_SCRATCH_BYTES; CROFT_ERR_INVALID_VALUE while
+ * per-pass profiling is enabled on the plan (it creates events); otherwise
+ * as croft_execute_scaled. */
+#define CROFT_NOALLOC_SCRATCH_BYTES (4u << 20)
+int croft_execute_scaled_noalloc(croft_plan_t plan, const void *in, const int8_t *in_exp, void *out,
+                                 int8_t *out_exp, hipStream_t stream);
+
 /* Free a plan and its device tables.  NULL is a no-op returning CROFT_SUCCESS. */
 int croft_plan_destroy(croft_plan_t plan);
 

@@ -39,8 +39,9 @@ EXPORTED = (
     "croft_plan_batched_offsets", "croft_execute_batched", "croft_plan_info",
     "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read",
     "croft_plan_create_real", "croft_plan_describe_real", "croft_plan_create_convolution",
-    "croft_execute_convolution", "croft_plan_describe_convolution",
+    "croft_execute_convolution", "croft_plan_describe_convolution", "croft_execute_scaled_noalloc",
 )
+CROFT_NOALLOC_SCRATCH_BYTES = 4 << 20
 
 
 class CroftError(RuntimeError):
@@ -97,6 +98,8 @@ def load():
     lib.croft_execute.restype = i
     lib.croft_execute_scaled.argtypes = [p, vp, vp, vp, vp, vp]
     lib.croft_execute_scaled.restype = i
+    lib.croft_execute_scaled_noalloc.argtypes = [p, vp, vp, vp, vp, vp]
+    lib.croft_execute_scaled_noalloc.restype = i
     lib.croft_plan_destroy.argtypes = [p]
     lib.croft_plan_destroy.restype = i
     lib.croft_last_error.argtypes = []
@@ -184,6 +187,11 @@ def croft_execute(plan, inp, out, stream=None) -> None:
 def croft_execute_scaled(plan, inp, in_exp, out, out_exp, stream=None) -> None:
     _check(load().croft_execute_scaled(plan, _ptr(inp), _ptr(in_exp), _ptr(out), _ptr(out_exp),
                                        _stream(stream, inp, out)))
+
+
+def croft_execute_scaled_noalloc(plan, inp, in_exp, out, out_exp, stream=None) -> None:
+    _check(load().croft_execute_scaled_noalloc(plan, _ptr(inp), _ptr(in_exp), _ptr(out), _ptr(out_exp),
+                                               _stream(stream, inp, out)))
 
 
 def croft_plan_destroy(plan) -> None:

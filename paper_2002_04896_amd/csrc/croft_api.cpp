@@ -50,6 +50,7 @@ struct croft_plan {
     std::map<int, void *> twiddles;  // length -> device table
     std::map<int, std::pair<void *, void *>> bluestein;  // length -> (chirp, kernel DFT)
     int8_t *e1 = nullptr, *e2 = nullptr;  // half storage: exponents after x and y passes
+    int8_t *scratch = nullptr;            // half storage: this device's static scratch array
     size_t work_bytes = 0;
     // real transforms: grids[0] holds the real dimensions; the backward
     // direction runs its complex passes in `rwork` (the input is kept)
@@ -526,6 +527,9 @@ int attach_resources(croft_plan *p) {
             return fail(CROFT_ERR_OUT_OF_MEMORY, "exponent scratch: %s", hipGetErrorString(e));
         }
         p->work_bytes += b1 + b2;
+        // the allocation-free execute's exponents: the device's static array
+        if ((e = noalloc_scratch(p->device, &p->scratch)) != hipSuccess)
+            return fail_hip(e, "static scratch address");
     }
     if (p->slabs > 1 || (p->slab_auto && (p->flags & CROFT_MEASURE))) {
         for (int i = 0; i < 2; ++i) {
@@ -668,9 +672,10 @@ int measure_passes(croft_plan *p) {
 }
 
 int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp,
-             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof);
+             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof, int8_t *e1 = nullptr,
+             int8_t *e2 = nullptr);
 int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp, hipStream_t s,
-              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof);
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof, int8_t *e1 = nullptr, int8_t *e2 = nullptr);
 
 // The slab counts a grid can take: 1, 2, 4, 8, 16 where they divide nz.
 std::vector<int> slab_candidates(int nz) {
@@ -909,11 +914,15 @@ int run_pass(croft_plan *p, const PassLaunch &pl, const void *in, void *out, con
 }
 
 // Plain schedule of one grid: each pass over the whole grid, the first
-// reading `in`, the rest working in place on `out`.
+// reading `in`, the rest working in place on `out`.  Half storage: the
+// intermediate exponents go to e1 (after x) and e2 (after y); NULL takes the
+// plan's own arrays.
 int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp,
-             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+             hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof, int8_t *e1, int8_t *e2) {
     const std::vector<PassLaunch> &ps = p->passes[gi];
     const bool half = is_half(p->dtype);
+    if (!e1) e1 = p->e1;
+    if (!e2) e2 = p->e2;
     if (p->real && p->dir == CROFT_BACKWARD) {
         // complex passes from `in` into the work buffer, the real x pass from
         // there into `out`
@@ -931,8 +940,8 @@ int run_grid(croft_plan *p, size_t gi, const char *in, char *out, const int8_t *
         const int8_t *ie = nullptr;
         int8_t *oe = nullptr;
         if (half) {
-            ie = i == 0 ? in_exp : (i == 1 ? p->e1 : p->e2);
-            oe = i == 0 ? p->e1 : (i == 1 ? p->e2 : out_exp);
+            ie = i == 0 ? in_exp : (i == 1 ? e1 : e2);
+            oe = i == 0 ? e1 : (i == 1 ? e2 : out_exp);
         }
         const int rc = run_pass(p, ps[i], src, out, ie, oe, s, prof);
         if (rc != CROFT_SUCCESS) return rc;
@@ -961,9 +970,12 @@ int run_conv(croft_plan *p, const void *in, const void *mul, void *out, double *
 
 // Slab schedule (K = p->slabs): the x and y passes slab by slab along z on two
 // side streams, then the z pass over the whole grid on the caller's stream.
+// e1, e2 as for run_grid.
 int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, int8_t *out_exp, hipStream_t s,
-              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof, int8_t *e1, int8_t *e2) {
     const Geometry &g = p->grids[0];
+    if (!e1) e1 = p->e1;
+    if (!e2) e2 = p->e2;
     const std::vector<PassLaunch> &ps = p->passes[0];
     const bool half = is_half(p->dtype);
     const size_t eb = element_bytes(p->dtype);
@@ -992,10 +1004,10 @@ int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, in
                 // x pass: exponents per x-line (y + ny z); y pass: per y-line (x + nx z)
                 if (pl.axis == 0) {
                     ie = in_exp ? in_exp + z0 * g.ny : nullptr;
-                    oe = p->e1 + z0 * g.ny;
+                    oe = e1 + z0 * g.ny;
                 } else {
-                    ie = p->e1 + z0 * g.ny;
-                    oe = p->e2 + z0 * g.nx;
+                    ie = e1 + z0 * g.ny;
+                    oe = e2 + z0 * g.nx;
                 }
             }
             const int rc = run_pass(p, pl, src, out + off, ie, oe, ss, prof);
@@ -1008,7 +1020,7 @@ int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, in
     }
     if (zp) {
         const void *src = xy.empty() ? (const void *)in : (const void *)out;
-        const int rc = run_pass(p, *zp, src, out, half ? p->e2 : nullptr, half ? out_exp : nullptr, s, prof);
+        const int rc = run_pass(p, *zp, src, out, half ? e2 : nullptr, half ? out_exp : nullptr, s, prof);
         if (rc != CROFT_SUCCESS) return rc;
     }
     return CROFT_SUCCESS;
@@ -1097,14 +1109,14 @@ int check_buffers(croft_plan *p, const void *in, const void *out) {
 }
 
 int execute_any(croft_plan *p, const void *in, const int8_t *in_exp, void *out, int8_t *out_exp,
-                hipStream_t s) {
+                hipStream_t s, int8_t *e1 = nullptr, int8_t *e2 = nullptr) {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> rec;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof = p->profiling ? &rec : nullptr;
     int rc;
     if (p->slabs > 1)
-        rc = run_slabs(p, (const char *)in, (char *)out, in_exp, out_exp, s, prof);
+        rc = run_slabs(p, (const char *)in, (char *)out, in_exp, out_exp, s, prof, e1, e2);
     else
-        rc = run_grid(p, 0, (const char *)in, (char *)out, in_exp, out_exp, s, prof);
+        rc = run_grid(p, 0, (const char *)in, (char *)out, in_exp, out_exp, s, prof, e1, e2);
     if (prof) p->prof.push_back(std::move(rec));
     return rc;
 }
@@ -1256,6 +1268,30 @@ int croft_execute_scaled(croft_plan_t p, const void *in, const int8_t *in_exp, v
     const int rc = check_buffers(p, in, out);
     if (rc != CROFT_SUCCESS) return rc;
     return execute_any(p, in, in_exp, out, out_exp, stream);
+}
+
+int croft_execute_scaled_noalloc(croft_plan_t p, const void *in, const int8_t *in_exp, void *out, int8_t *out_exp,
+                                 hipStream_t stream) {
+    if (!p) return fail(CROFT_ERR_INVALID_VALUE, "NULL plan");
+    if (p->batched) return fail(CROFT_ERR_INVALID_VALUE, "batched plan: use croft_execute_batched");
+    if (!is_half(p->dtype))
+        return fail(CROFT_ERR_UNSUPPORTED_DTYPE, "croft_execute_scaled_noalloc needs a CROFT_C16F/CROFT_C16B plan");
+    if (!out_exp) return fail(CROFT_ERR_INVALID_VALUE, "NULL out_exp");
+    if (p->profiling)
+        return fail(CROFT_ERR_INVALID_VALUE, "per-pass profiling creates events: disable it for the "
+                                             "allocation-free execute");
+    const Geometry &g = p->grids[0];
+    const size_t b1 = (size_t)g.ny * g.nz, b2 = (size_t)g.nx * g.nz;
+    const size_t off2 = (b1 + 255) / 256 * 256;
+    if (off2 + b2 > kNoAllocScratchBytes)
+        return fail(CROFT_ERR_UNSUPPORTED_SIZE,
+                    "grid %dx%dx%d needs %zu bytes of exponent scratch (ny*nz + nx*nz, the first rounded up to "
+                    "256); the static array holds %zu",
+                    g.nx, g.ny, g.nz, off2 + b2, kNoAllocScratchBytes);
+    if (!p->scratch) return fail(CROFT_ERR_INTERNAL, "no static scratch address for the plan's device");
+    const int rc = check_buffers(p, in, out);
+    if (rc != CROFT_SUCCESS) return rc;
+    return execute_any(p, in, in_exp, out, out_exp, stream, p->scratch, p->scratch + off2);
 }
 
 croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, int dir, int flags) {

@@ -154,6 +154,15 @@ hipError_t launch_batch_coop(const void *items, const int item_begin[4], const l
 hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t lds, int dtype, int inverse,
                         const void *in, void *out, hipStream_t stream);
 
+// ---- allocation-free half-storage execute (croft_noalloc.hip) ----
+// Bytes of the static per-GPU scratch array that holds the intermediate
+// exponents of croft_execute_scaled_noalloc.
+constexpr size_t kNoAllocScratchBytes = (size_t)4 << 20;
+// The address of `device`'s copy of that array (looked up with
+// hipGetSymbolAddress on the first call for a device, which must then be
+// the current one; cached afterwards).
+hipError_t noalloc_scratch(int device, int8_t **ptr);
+
 // ---- wisdom (croft_tune.cpp) ----
 // dir: -1 forward, +1 backward, 0 a pass that runs in both directions (the
 // forward-only built-in choices apply to -1 only).  axis: the grid axis of a
