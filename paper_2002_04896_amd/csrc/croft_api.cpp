@@ -441,7 +441,7 @@ int attach_resources(croft_plan *p) {
                 e = hipMemcpy(d, w.data(), bytes, hipMemcpyHostToDevice);
             } else {
                 std::vector<float> f(w.size());
-                for (size_t i = 0; i < w.size(); ++i) f[i] = (float)w[i];  // round to nearest even
+                round_to_fp32(w.data(), w.size(), f.data());
                 e = hipMemcpy(d, f.data(), bytes, hipMemcpyHostToDevice);
             }
             if (e != hipSuccess) return fail_hip(e, "twiddle upload");
@@ -463,7 +463,7 @@ int attach_resources(croft_plan *p) {
             e = hipMemcpy(*out, v.data(), bytes, hipMemcpyHostToDevice);
         } else {
             std::vector<float> f(v.size());
-            for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+            round_to_fp32(v.data(), v.size(), f.data());
             e = hipMemcpy(*out, f.data(), bytes, hipMemcpyHostToDevice);
         }
         return e == hipSuccess ? CROFT_SUCCESS : fail_hip(e, "Bluestein table upload");

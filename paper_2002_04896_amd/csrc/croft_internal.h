@@ -182,6 +182,9 @@ int factorize(int n, int *radix);  // returns stage count, 0 if unsupported
 // Forward twiddles w[m] = exp(-2 pi i m / n), m < n, computed in FP64 with
 // octant symmetry, written as interleaved doubles (2n values).
 void twiddles_fp64(int n, double *out);
+// out[i] = in[i] rounded to nearest even FP32 (the tables of FP32-compute
+// plans are the FP64 values rounded once).
+void round_to_fp32(const double *in, size_t count, float *out);
 // Bluestein's tables for length n and convolution length m >= 2n - 1:
 // chirp[j] = exp(-pi i j^2 / n), j < n (2n doubles), and bhat = the m-point
 // DFT of b, b[i] = b[m - i] = conj chirp[i] for i < n (zero elsewhere),

@@ -72,6 +72,12 @@ void twiddles_fp64(int n, double *out) {
     }
 }
 
+// The FP64 values rounded once, to nearest even, to the FP32 the c64 and
+// half-storage kernels compute in.
+void round_to_fp32(const double *in, size_t count, float *out) {
+    for (size_t i = 0; i < count; ++i) out[i] = static_cast<float>(in[i]);
+}
+
 int bluestein_length(int n) {
     int m = 1;
     while (m < 2 * n - 1) m *= 2;
