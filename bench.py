@@ -9,6 +9,12 @@ already resident in HBM; `value` is GFLOP/s by the 5 N log2 N convention.
 
 The dominant kernel's roofline uses HIP events recorded by the library around
 each pass launch on the stream the pass runs on, over the timed region.
+After all GPU timing, the CPU leg times the FP64 oracle on a bounded sample
+(`cpu_baseline`) and compares exact oracle output lines with the GPU's
+results (`oracle_check`: the complex64 headline, complex128, both 16-bit
+storage forms, the 64-grid batch and the 1024^3 grid).  `--no-coop` leaves
+out the batched form's cooperative launch (profiled runs: rocprofv3 has
+ended in a segmentation fault at exit in runs that included it).
 `--calibrate-copy` instead times a plain device copy of the same bytes (used
 to scale the HBM byte counters).  The line also carries the half-storage
 (FP16, BF16 at 512^3) and batched (64 uneven grids) forms, each timed next to
@@ -64,29 +70,79 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--only-form", choices=["half"], default=None,
                     help="time one form alone (for profiling) and print it")
+    ap.add_argument("--no-coop", action="store_true",
+                    help="skip the batched form's cooperative single launch")
     return ap.parse_args()
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_c64, n):
-    """Time the FP64 oracle on a bounded sample: 1/4 of the lines of every
-    axis, then extrapolate to the whole transform."""
+    """Time the FP64 oracle (naive O(n^2) DFT per line, Eq. 1) on a bounded
+    sample of the 512^3 transform: half of the lines of every axis, in place.
+    The rate is that of the sample: 5 N log2 N times the fraction of the work
+    done, over the measured seconds."""
     import numpy as np
     import oracle
 
     a = x_c64.astype(np.complex128)
     lines = n * n
-    sample = lines // 4
+    sample = lines // 2
     t0 = time.perf_counter()
     for axis in range(3):
         oracle.dft_axis_lines(a, axis, 0, sample, -1)
     dt = time.perf_counter() - t0
-    t_full = dt * (lines / sample)
+    frac = sample / lines
     N = n ** 3
-    return {"value": flops_5nlogn(N) / t_full / 1e9, "unit": "GFLOP/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"naive FP64 DFT of {sample} of the {lines} lines of each axis (1/4) of the "
-                      f"{n}^3 PME grid, {dt:.1f} s measured, whole transform extrapolated "
-                      f"({t_full:.1f} s)"}
+    work = flops_5nlogn(N) * frac
+    true_flops = 8.0 * N * 3 * n * frac            # one complex multiply-add per term: 8 flops
+    return {"value": work / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "measured_s": dt, "true_GFLOPs": true_flops / dt / 1e9,
+            "sample": f"naive FP64 DFT of {sample} of the {lines} lines of each axis ({frac:g} of the work) "
+                      f"of the {n}^3 PME grid, in place, {dt:.1f} s on {oracle.max_threads()} threads; "
+                      f"value = 5 N log2 N x {frac:g} / {dt:.1f} s (a rate, not extrapolated)"}
+
+
+def sample_pairs(ny, nz, count, seed):
+    """(ky, kz) output lines to check: the corners plus seeded random ones."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = [(0, 0), (ny - 1, nz - 1), (ny // 2, nz // 3)]
+    pts += [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, count - 3), rng.integers(0, nz, count - 3))]
+    return pts
+
+
+def device_lines(t, kyz):
+    """Lines Y(., ky, kz) of a (nz, ny, nx[, 2]) device tensor, to the host."""
+    import torch
+    kz = torch.tensor([b for _, b in kyz], device=t.device)
+    ky = torch.tensor([a for a, _ in kyz], device=t.device)
+    return t[kz, ky].cpu().numpy()
+
+
+def oracle_checks(checks):
+    """Compare every collected GPU result with exact FP64 oracle lines (the
+    CPU leg: runs after all GPU timing).  Each check is a dict with a
+    `compute` callable returning (GPU lines, oracle lines) and a tolerance."""
+    import oracle
+    out = {}
+    for c in checks:
+        t0 = time.perf_counter()
+        got, ref = c["compute"](oracle)
+        err = oracle.rel_l2(got, ref)
+        out[c["name"]] = {"rel_l2": err, "tol": c["tol"], "ok": bool(err <= c["tol"]), "lines": c["lines"],
+                          "what": c["what"], "oracle_s": time.perf_counter() - t0}
+    return out
 
 
 def calibrate_copy(torch, steps, warmup):
@@ -222,10 +278,12 @@ def measure_conv(torch, np, croft, synth, pme, steps):
     return res
 
 
-def measure_large(torch, np, croft, pme, steps):
+def measure_large(torch, np, croft, pme, steps, checks):
     """A 1024^3 complex64 PME grid (8 GiB), forward, out of place: the 512^3
     PME grid repeated 2 x 2 x 2 on the device (a periodic charge grid of the
-    same density; generating a fresh 1024^3 grid on the host takes a minute)."""
+    same density; generating a fresh 1024^3 grid on the host takes a minute).
+    Its exact lines follow from the 512^3 grid's: the repeated grid's
+    transform is 8 Y512(k/2) where every component of k is even, else 0."""
     n = 1024
     half = torch.from_numpy(pme).cuda()
     d_in = half.repeat(2, 2, 2)
@@ -237,12 +295,54 @@ def measure_large(torch, np, croft, pme, steps):
     ms, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out), steps, 2, 3)
     croft.croft_plan_destroy(plan)
     dc = d_out[0, 0, 0].item()
+    half_pairs = sample_pairs(n // 2, n // 2, 8, seed=12)
+    kyz = [(2 * a, 2 * b) for a, b in half_pairs] + [(1, 0), (n - 2, 3)]
+    got = device_lines(d_out, kyz)
     del d_in, d_out
     torch.cuda.empty_cache()
+
+    def compute(o):
+        y512 = o.dft3d_lines(pme, half_pairs, -1)
+        ref = np.zeros((len(kyz), n), np.complex128)
+        ref[: len(half_pairs), 0::2] = 8.0 * y512
+        return got, ref
+    checks.append({"name": "c64_1024cube", "compute": compute, "tol": 1e-5, "lines": len(kyz),
+                   "what": "8 lines with even (ky, kz) from 8 x the oracle lines of the 512^3 grid at "
+                           "half the frequencies, 2 lines with an odd component (exactly zero)"})
     return {"ms": ms, "GFLOPs": flops_5nlogn(n ** 3) / ms / 1e6,
             "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
             "effective_frac_of_8TBps": info["algorithmic_bytes"] / ms / 1e6 / HBM_PEAK_GBPS, "pass_ms": pm,
             "dc_minus_total_charge": dc.real - qtot}
+
+
+def measure_c128(torch, np, croft, pme, steps, checks):
+    """The paper's own precision (double complex, Section 5): forward 512^3
+    complex128 on the same PME grid, FP64 compute, with the roofline of its
+    dominant pass (2 N 16 bytes per launch against 8 TB/s)."""
+    n = pme.shape[0]
+    N = n ** 3
+    d_in = torch.from_numpy(pme.astype(np.complex128)).cuda()
+    d_out = torch.empty_like(d_in)
+    plan = croft.croft_plan_create(n, n, n, croft.CROFT_C128, croft.CROFT_FORWARD)
+    info = croft.croft_plan_info(plan)
+    ms, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out), steps, 3, 3)
+    croft.croft_plan_destroy(plan)
+    kyz = sample_pairs(n, n, 8, seed=13)
+    got = device_lines(d_out, kyz)
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    checks.append({"name": "c128_512cube", "compute": lambda o: (got, o.dft3d_lines(pme, kyz, -1)),
+                   "tol": 1e-12, "lines": len(kyz), "what": "exact oracle lines of the complex128 transform"})
+    dom = max(range(3), key=lambda i: pm[i])
+    per_launch = 2.0 * N * 16
+    achieved = per_launch / pm[dom] / 1e6
+    return {"ms": ms, "GFLOPs": flops_5nlogn(N) / ms / 1e6,
+            "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
+            "effective_frac_of_8TBps": info["algorithmic_bytes"] / ms / 1e6 / HBM_PEAK_GBPS, "pass_ms": pm,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                         "kernel": f"pass {'xyz'[dom]}", "bytes_per_launch": per_launch,
+                         "avg_launch_ms": pm[dom]}}
 
 
 def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
@@ -373,7 +473,7 @@ def measure_shard_share(torch, np, croft, steps):
     return out
 
 
-def measure_forms(torch, np, croft, synth, steps, only=None):
+def measure_forms(torch, np, croft, synth, steps, checks, only=None, coop=True):
     """Half-storage (512^3) and batched (64 uneven grids) forms, each timed
     next to the plain complex64 form on the same input and GPU, with its error
     against that form (only="half": the half-storage forms alone)."""
@@ -413,6 +513,17 @@ def measure_forms(torch, np, croft, synth, steps, only=None):
         croft.croft_plan_destroy(cplan)
         got = (d_out.float()[..., 0] + 1j * d_out.float()[..., 1]) * torch.pow(2.0, e_out.float())[None, :, :]
         err = rel_l2_dev(torch, got, c_out)
+        kyz = sample_pairs(n, n, 8, seed=14)
+        bits = device_lines(d_out.view(torch.int16), kyz).view(np.uint16)      # (8, nx, 2)
+        oe = e_out.cpu().numpy()
+        line_exp = np.stack([oe[ky] for ky, _ in kyz])                       # z-line exponents (x)
+
+        def compute(o, data=data, e=e, kind=kind, kyz=kyz, bits=bits, line_exp=line_exp):
+            # sampled line i holds the z-lines (x, ky_i): exponents oe[ky_i, :]
+            gl = o.decode_half(bits[:, None], line_exp, kind, 1)[:, 0]
+            return gl, o.dft3d_lines(o.decode_half(data, e, kind, 0), kyz, -1)
+        checks.append({"name": name, "compute": compute, "tol": 5e-3, "lines": len(kyz),
+                       "what": "exact oracle lines of the decoded stored input"})
         err_orig = rel_l2_dev(torch, got, orig_out)
         out[name] = {"ms": ms, "GFLOPs": flops_5nlogn(N) / ms / 1e6,
                      "effective_GBps": info["algorithmic_bytes"] / ms / 1e6, "pass_ms": pm,
@@ -420,7 +531,7 @@ def measure_forms(torch, np, croft, synth, steps, only=None):
                      "rel_l2_vs_c64_of_unquantised_input": err_orig}
         del d_in, d_out, vals, c_out, got
         torch.cuda.empty_cache()
-    del v, orig_out
+    del orig_out
     torch.cuda.empty_cache()
     if only == "half":
         return out
@@ -448,8 +559,9 @@ def measure_forms(torch, np, croft, synth, steps, only=None):
         croft.croft_plan_destroy(plan)
         return a_.elapsed_time(b_) / steps, info
     ms, info = time_batched(0, d_out)
-    d_coop = torch.empty_like(d_in)
-    ms_coop, _ = time_batched(croft.CROFT_PERSISTENT, d_coop)
+    if coop:
+        d_coop = torch.empty_like(d_in)
+        ms_coop, _ = time_batched(croft.CROFT_PERSISTENT, d_coop)
     # the same grids as separate plain plans on one stream
     plans = [croft.croft_plan_create(int(a), int(b), int(c), croft.CROFT_C64, croft.CROFT_FORWARD)
              for a, b, c in dims]
@@ -474,9 +586,25 @@ def measure_forms(torch, np, croft, synth, steps, only=None):
     out["batched_64"] = {"ms": ms, "GFLOPs": fl / ms / 1e6, "elements": int(flat.size),
                          "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
                          "plain_calls_ms": ms_plain, "speedup_vs_plain_calls": ms_plain / ms,
-                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref)),
-                         "cooperative_ms": ms_coop,
-                         "cooperative_bitwise_equal": bool(torch.equal(d_coop, d_out))}
+                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref))}
+    if coop:
+        out["batched_64"]["cooperative_ms"] = ms_coop
+        out["batched_64"]["cooperative_bitwise_equal"] = bool(torch.equal(d_coop, d_out))
+    # two exact lines per grid
+    host_out = d_out.cpu().numpy()
+    per = []
+    for i, (a, b, c) in enumerate(dims):
+        nx, ny, nz = int(a), int(b), int(c)
+        kyz = sample_pairs(ny, nz, 3, seed=500 + i)[:2]
+        g = host_out[offs[i]:offs[i + 1]].reshape(nz, ny, nx)
+        per.append((flat[offs[i]:offs[i + 1]].reshape(nz, ny, nx), kyz, np.stack([g[kz, ky] for ky, kz in kyz])))
+
+    def compute(o):
+        got = np.concatenate([gl.ravel() for _, _, gl in per])
+        ref = np.concatenate([o.dft3d_lines(x, kyz, -1).ravel() for x, kyz, _ in per])
+        return got, ref
+    checks.append({"name": "batched_64", "compute": compute, "tol": 1e-5, "lines": 2 * len(dims),
+                   "what": "2 exact oracle lines of each of the 64 grids"})
     return out
 
 
@@ -495,8 +623,9 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(torch, args.steps, args.warmup)
         return
+    checks = []
     if args.only_form == "half":
-        print(json.dumps({"forms": measure_forms(torch, np, croft, synth, args.steps, only="half")}))
+        print(json.dumps({"forms": measure_forms(torch, np, croft, synth, args.steps, checks, only="half")}))
         return
 
     n = args.size
@@ -514,6 +643,10 @@ def main():
     # sanity: DC bin equals the total charge
     dc = d_out[0, 0, 0].item()
     croft.croft_plan_destroy(plan)
+    kyz = sample_pairs(n, n, 8, seed=11)
+    head_lines = device_lines(d_out, kyz)
+    checks.append({"name": f"c64_{n}cube", "compute": lambda o: (head_lines, o.dft3d_lines(x, kyz, -1)),
+                   "tol": 1e-5, "lines": len(kyz), "what": "exact oracle lines of the headline transform"})
     copy_gbps = copy_bandwidth(torch)
 
     gflops = flops_5nlogn(N) / ms / 1e6
@@ -553,11 +686,16 @@ def main():
         torch.cuda.empty_cache()
         line["forms"] = measure_real(torch, np, croft, x, max(10, args.steps // 2))
         line["forms"]["convolution"] = measure_conv(torch, np, croft, synth, x, max(10, args.steps // 2))
-        line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5))
-        line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2)))
+        line["forms"]["c128_512cube"] = measure_c128(torch, np, croft, x, max(10, args.steps // 2), checks)
+        line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5), checks)
+        line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2), checks,
+                                           coop=not args.no_coop))
         line["configs"] = measure_configs(torch, np, croft, synth)
         line["forms"]["shard_share_1024cube_8gpu"] = measure_shard_share(torch, np, croft, max(5, args.steps // 5))
     if not args.no_cpu_baseline:
+        # the CPU leg, after every GPU measurement: the oracle's own rate on
+        # a bounded sample, and exact oracle lines against each GPU result
+        line["oracle_check"] = oracle_checks(checks)
         line["cpu_baseline"] = cpu_baseline(x, n)
     print(json.dumps(line))
 
