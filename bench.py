@@ -559,6 +559,9 @@ def measure_forms(torch, np, croft, synth, steps, checks, only=None, coop=True):
         croft.croft_plan_destroy(plan)
         return a_.elapsed_time(b_) / steps, info
     ms, info = time_batched(0, d_out)
+    # tile shapes chosen by the autotuner on this GPU (nothing read or written to a wisdom file)
+    d_meas = torch.empty_like(d_in)
+    ms_meas, _ = time_batched(croft.CROFT_MEASURE | croft.CROFT_NO_WISDOM, d_meas)
     if coop:
         d_coop = torch.empty_like(d_in)
         ms_coop, _ = time_batched(croft.CROFT_PERSISTENT, d_coop)
@@ -586,7 +589,9 @@ def measure_forms(torch, np, croft, synth, steps, checks, only=None, coop=True):
     out["batched_64"] = {"ms": ms, "GFLOPs": fl / ms / 1e6, "elements": int(flat.size),
                          "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
                          "plain_calls_ms": ms_plain, "speedup_vs_plain_calls": ms_plain / ms,
-                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref))}
+                         "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref)),
+                         "measured_shapes_ms": ms_meas,
+                         "measured_shapes_bitwise_equal": bool(torch.equal(d_meas, d_out))}
     if coop:
         out["batched_64"]["cooperative_ms"] = ms_coop
         out["batched_64"]["cooperative_bitwise_equal"] = bool(torch.equal(d_coop, d_out))

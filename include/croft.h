@@ -91,9 +91,11 @@ enum croft_flags {
     CROFT_NO_WISDOM = 4,      /* MEASURE: neither read nor write the wisdom file */
     CROFT_PERSISTENT = 8      /* batched plans: one cooperative launch for every pass of every
                                  grid (all blocks resident, looping over the tiles of pass 0, a
-                                 grid-wide barrier, pass 1, a barrier, pass 2) instead of one
-                                 launch per pass.  Issued directly on the stream, not through the
-                                 plan's graph; same results bit for bit. */
+                                 grid-wide barrier, pass 1, a barrier, pass 2) instead
+                                 of one launch per pass.  Replayed from the plan's graph like the
+                                 per-pass form (issued directly if the runtime cannot capture a
+                                 cooperative launch: croft_plan_info.cooperative_captured); same
+                                 results bit for bit. */
 };
 
 /* Create a plan for one nx x ny x nz transform (the paper's problem statement,
@@ -279,6 +281,9 @@ struct croft_plan_info {
     double flops;             /* sum over grids of 5 N log2 N (real plans: 2.5 N log2 N) */
     int real;                 /* 1 for a plan of croft_plan_create_real or _convolution */
     int convolution;          /* 1 for a plan of croft_plan_create_convolution */
+    int cooperative_captured; /* batched CROFT_PERSISTENT plans: 1 once the cooperative launch
+                                 runs from the plan's graph, 0 if it is issued directly, -1
+                                 before the first execute (and for other plans) */
 };
 int croft_plan_info(croft_plan_t plan, struct croft_plan_info *info);
 

@@ -64,7 +64,8 @@ class PlanInfo(ctypes.Structure):
                 ("pass_", PassInfo * CROFT_MAX_PASSES),
                 ("elements", ctypes.c_size_t), ("element_bytes", ctypes.c_size_t),
                 ("work_bytes", ctypes.c_size_t), ("algorithmic_bytes", ctypes.c_double),
-                ("flops", ctypes.c_double), ("real", ctypes.c_int), ("convolution", ctypes.c_int)]
+                ("flops", ctypes.c_double), ("real", ctypes.c_int), ("convolution", ctypes.c_int),
+                ("cooperative_captured", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pass_"}

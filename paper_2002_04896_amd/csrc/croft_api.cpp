@@ -72,7 +72,10 @@ struct croft_plan {
     long long btiles[3] = {0, 0, 0};   // tiles of pass p
     size_t blds[3] = {0, 0, 0};
     int bresident = 0;                 // cooperative launch: blocks the device holds at once
+    bool coop_direct = false;          // cooperative launch issued directly: it could not be captured
     std::vector<size_t> loose;  // grids run with their own launches
+    std::vector<size_t> bgrids;  // grids the batched kernel runs
+    std::map<std::pair<int, int>, int> bshape;  // (length, kind) -> tile shape of the batched kernel
     // batched form: graph cache
     hipGraphExec_t graph = nullptr;
     const void *graph_in = nullptr;
@@ -752,27 +755,24 @@ int measure_slabs(croft_plan *p) {
 }
 
 // Batched plans: the segment table of the batched kernels (one segment per
-// grid and pass, pass by pass), and the cooperative launch's grid size.
-int build_batch_tables(croft_plan *p) {
-    const bool usable = (p->dtype == CROFT_C64 || p->dtype == CROFT_C128) && !(p->flags & CROFT_FORCE_GENERIC);
+// grid and pass, pass by pass) for the plan's tile shapes, uploaded; the
+// launch LDS of each pass and the cooperative launch's grid size.
+int upload_batch_tables(croft_plan *p) {
     const size_t ib = batch_item_bytes();
-    std::vector<size_t> grids;  // grids in the table
-    for (size_t g = 0; g < p->grids.size(); ++g) {
-        const std::vector<PassLaunch> &ps = p->passes[g];
-        bool ok = usable && ps.size() <= 3;
-        for (const PassLaunch &pl : ps) ok = ok && batch_code(pl.n, pl.kind) >= 0;
-        (ok ? grids : p->loose).push_back(g);
-    }
     std::vector<char> host;
     int nseg = 0;
     for (int i = 0; i < 3; ++i) {
+        p->btiles[i] = 0;
+        p->blds[i] = 0;
+    }
+    for (int i = 0; i < 3; ++i) {
         p->bbegin[i] = nseg;
-        for (size_t g : grids) {
+        for (size_t g : p->bgrids) {
             const std::vector<PassLaunch> &ps = p->passes[g];
             if ((size_t)i >= ps.size()) continue;
             const PassLaunch &pl = ps[i];
             BatchConfig bc;
-            const int code = batch_code(pl.n, pl.kind);
+            const int code = batch_code(pl.n, pl.kind, p->bshape[{pl.n, pl.kind}]);
             if (!batch_config(code, p->dtype, &bc)) return fail(CROFT_ERR_INTERNAL, "batch configuration %d", code);
             long long ntiles, total;
             if (pl.kind == kContiguous) {
@@ -792,12 +792,15 @@ int build_batch_tables(croft_plan *p) {
     }
     p->bbegin[3] = nseg;
     if (!nseg) return CROFT_SUCCESS;
-    hipError_t e = hipMalloc(&p->bitems, host.size());
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(CROFT_ERR_OUT_OF_MEMORY, "batch tables: %s", hipGetErrorString(e));
+    hipError_t e;
+    if (!p->bitems) {
+        // every shape choice gives the same number of segments
+        if ((e = hipMalloc(&p->bitems, host.size())) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "batch tables: %s", hipGetErrorString(e));
+        }
+        p->work_bytes += host.size();
     }
-    p->work_bytes += host.size();
     if ((e = hipMemcpy(p->bitems, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail_hip(e, "batch table upload");
     const size_t lds = std::max({p->blds[0], p->blds[1], p->blds[2]});
@@ -819,6 +822,92 @@ int build_batch_tables(croft_plan *p) {
     if (nb < 1) return fail(CROFT_ERR_INTERNAL, "the cooperative batched kernel cannot be resident");
     p->bresident = nb * std::max(1, device_cus());
     return CROFT_SUCCESS;
+}
+
+int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
+              std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof);
+
+// CROFT_MEASURE on a batched plan: for each (length, kind) of the batched
+// kernel in the batch, time the whole batch (its own launch form) with each
+// compiled tile shape of that pair, the others at their current choice; keep
+// the fastest (best of five) and record it as wisdom (kind 4 + kind).
+int measure_batch_shapes(croft_plan *p) {
+    const size_t bytes = p->offsets.back() * element_bytes(p->dtype);
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    auto cleanup = [&]() {
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    };
+    hipError_t e;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(CROFT_ERR_OUT_OF_MEMORY, "batch autotune scratch of %zu bytes", 2 * bytes);
+    }
+    if ((e = hipMemset(a, 0, bytes)) != hipSuccess || (e = hipEventCreate(&t0)) != hipSuccess ||
+        (e = hipEventCreate(&t1)) != hipSuccess) {
+        cleanup();
+        return fail_hip(e, "batch autotune setup");
+    }
+    int rc = CROFT_SUCCESS;
+    const bool persist = !(p->flags & CROFT_NO_WISDOM);
+    for (auto &kv : p->bshape) {
+        float best = 1e30f;
+        int pick = kv.second;
+        for (int shape = 0; shape < batch_shape_count(p->dtype) && rc == CROFT_SUCCESS; ++shape) {
+            kv.second = shape;
+            if ((rc = upload_batch_tables(p)) != CROFT_SUCCESS) break;
+            if ((rc = run_batch(p, a, b, nullptr, nullptr)) != CROFT_SUCCESS) break;  // warm-up
+            float best_rep = 1e30f;
+            for (int rep = 0; rep < 5 && rc == CROFT_SUCCESS; ++rep) {
+                float ms = 0.f;
+                e = hipEventRecord(t0, nullptr);
+                if (e == hipSuccess && (rc = run_batch(p, a, b, nullptr, nullptr)) != CROFT_SUCCESS) break;
+                if (e == hipSuccess) e = hipEventRecord(t1, nullptr);
+                if (e == hipSuccess) e = hipEventSynchronize(t1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+                if (e != hipSuccess) rc = fail_hip(e, "batch autotune timing");
+                best_rep = std::min(best_rep, ms);
+            }
+            if (best_rep < best) {
+                best = best_rep;
+                pick = shape;
+            }
+        }
+        if (rc != CROFT_SUCCESS) break;
+        kv.second = pick;
+        wisdom_record(kv.first.first, kBatchWisdomKind + kv.first.second, p->dtype, -1, pick, 0, persist);
+    }
+    cleanup();
+    if (rc != CROFT_SUCCESS) return rc;
+    return upload_batch_tables(p);
+}
+
+// Batched plans: which grids the batched kernel runs (the others run with
+// launches of their own), each (length, kind)'s tile shape (wisdom, else
+// shape 0; CROFT_MEASURE times them), and the uploaded tables.
+int build_batch_tables(croft_plan *p) {
+    const bool usable = (p->dtype == CROFT_C64 || p->dtype == CROFT_C128) && !(p->flags & CROFT_FORCE_GENERIC);
+    for (size_t g = 0; g < p->grids.size(); ++g) {
+        const std::vector<PassLaunch> &ps = p->passes[g];
+        bool ok = usable && ps.size() <= 3;
+        for (const PassLaunch &pl : ps) ok = ok && batch_code(pl.n, pl.kind) >= 0;
+        (ok ? p->bgrids : p->loose).push_back(g);
+    }
+    for (size_t g : p->bgrids)
+        for (const PassLaunch &pl : p->passes[g]) {
+            int shape = 0, waves = 0;
+            if (!wisdom_lookup(pl.n, kBatchWisdomKind + pl.kind, p->dtype, p->dir, -1, &shape, &waves) || shape < 0 ||
+                shape >= batch_shape_count(p->dtype))
+                shape = 0;
+            p->bshape[{pl.n, pl.kind}] = shape;
+        }
+    int rc = upload_batch_tables(p);
+    if (rc == CROFT_SUCCESS && (p->flags & CROFT_MEASURE) && p->bbegin[3] > 0) rc = measure_batch_shapes(p);
+    return rc;
 }
 
 croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int flags, int slabs,
@@ -1048,7 +1137,8 @@ int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
         if (p->flags & CROFT_PERSISTENT) {
             const size_t lds = std::max({p->blds[0], p->blds[1], p->blds[2]});
             const long long most = std::max({p->btiles[0], p->btiles[1], p->btiles[2]});
-            const int blocks = (int)std::min<long long>(p->bresident, most);
+            // one block per CU: the grid-wide barriers cost more with more blocks
+            const int blocks = (int)std::min<long long>({(long long)p->bresident, (long long)std::max(1, device_cus()), most});
             e = launch_batch_coop(p->bitems, p->bbegin, p->btiles, blocks, lds, p->dtype, inv, in, out, s);
         } else {
             e = launch_batch((const char *)p->bitems + (size_t)p->bbegin[i] * ib, n, p->btiles[i], p->blds[i],
@@ -1355,9 +1445,9 @@ int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t
         p->prof.push_back(std::move(rec));
         return rc;
     }
-    // the cooperative launch is issued directly (one launch already), the
-    // per-pass launches through the captured graph
-    if (p->flags & CROFT_PERSISTENT) return run_batch(p, in, out, stream, nullptr);
+    // both forms are replayed from a graph captured on first use; a
+    // cooperative launch the runtime refuses to capture is issued directly
+    if (p->coop_direct) return run_batch(p, in, out, stream, nullptr);
     if (!p->graph || p->graph_in != in || p->graph_out != out || p->graph_stream != stream) {
         if (p->graph) {
             (void)hipGraphExecDestroy(p->graph);
@@ -1375,6 +1465,12 @@ int croft_execute_batched(croft_plan_t p, const void *in, void *out, hipStream_t
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cap, &graph);
         (void)hipStreamDestroy(cap);
+        if ((rc != CROFT_SUCCESS || e != hipSuccess) && (p->flags & CROFT_PERSISTENT)) {
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            p->coop_direct = true;
+            return run_batch(p, in, out, stream, nullptr);
+        }
         if (rc != CROFT_SUCCESS) {
             if (graph) (void)hipGraphDestroy(graph);
             return rc;
@@ -1436,6 +1532,10 @@ int croft_plan_info(croft_plan_t p, struct croft_plan_info *info) {
         if (n > 1) fl += 5.0 * n * std::log2(n);
     }
     info->flops = fl;
+    info->cooperative_captured = !(p->batched && (p->flags & CROFT_PERSISTENT)) ? -1
+                                 : p->coop_direct                              ? 0
+                                 : p->graph                                    ? 1
+                                                                               : -1;
     if (p->real) {
         size_t rb, sb;
         real_bytes(p, &rb, &sb);

@@ -13,28 +13,32 @@ using namespace dev;
 namespace {
 }  // namespace
 
-int batch_code(int n, int kind) {
+int batch_code(int n, int kind, int shape) {
+    if (shape < 0 || shape >= kBatchShapes) return -1;
     for (int i = 0; i < 8; ++i)
-        if (kBatchLengths[i] == n) return 2 * i + (kind == kStrided ? 1 : 0);
+        if (kBatchLengths[i] == n) return 2 * i + (kind == kStrided ? 1 : 0) + 16 * shape;
     return -1;
 }
 
 namespace {
 template <class St>
 void config_of(int code, BatchConfig *c) {
-    const int i = code / 2;
+    const int i = (code % 16) / 2;
     const int kind = code % 2;
+    const int shape = code / 16;
     c->n = kBatchLengths[i];
     c->kind = kind;
-    c->threads_per_line = batch_threads(c->n);
+    c->shape = shape;
+    c->threads_per_line = batch_threads(c->n, shape);
     c->lines = 256 / c->threads_per_line;
-    // same formula as SCfg::kLds for these configurations
     size_t lds = 0;
     switch (code) {
-#define CROFT_LDS(I)                                                   \
-    case 2 * I: lds = BCfg<kBatchLengths[I], kContiguous, St>::kLds; break; \
-    case 2 * I + 1: lds = BCfg<kBatchLengths[I], kStrided, St>::kLds; break;
-        CROFT_LDS(0) CROFT_LDS(1) CROFT_LDS(2) CROFT_LDS(3) CROFT_LDS(4) CROFT_LDS(5) CROFT_LDS(6) CROFT_LDS(7)
+#define CROFT_LDS(I, SH)                                                               \
+    case 2 * I + 16 * SH: lds = BCfg<kBatchLengths[I], kContiguous, St, SH>::kLds; break; \
+    case 2 * I + 1 + 16 * SH: lds = BCfg<kBatchLengths[I], kStrided, St, SH>::kLds; break;
+        CROFT_LDS(0, 0) CROFT_LDS(1, 0) CROFT_LDS(2, 0) CROFT_LDS(3, 0) CROFT_LDS(4, 0) CROFT_LDS(5, 0)
+        CROFT_LDS(6, 0) CROFT_LDS(7, 0) CROFT_LDS(0, 1) CROFT_LDS(1, 1) CROFT_LDS(2, 1) CROFT_LDS(3, 1)
+        CROFT_LDS(4, 1) CROFT_LDS(5, 1) CROFT_LDS(6, 1) CROFT_LDS(7, 1)
 #undef CROFT_LDS
         default: break;
     }
@@ -43,11 +47,15 @@ void config_of(int code, BatchConfig *c) {
 }  // namespace
 
 bool batch_config(int code, int dtype, BatchConfig *c) {
-    if (code < 0 || code >= 16) return false;
+    if (code < 0 || code >= 16 * batch_shape_count(dtype)) return false;
     if (dtype == kC64) config_of<StC64>(code, c);
     else if (dtype == kC128) config_of<StC128>(code, c);
     else return false;
     return true;
+}
+
+int batch_shape_count(int dtype) {
+    return dtype == kC64 ? batch_shapes<StC64>() : (dtype == kC128 ? batch_shapes<StC128>() : 0);
 }
 
 const void *batch_kernel(int dtype, int inverse) {

@@ -1326,7 +1326,7 @@ struct BatchItem {
     long long tile_begin;  // first tile of this segment within the launch
     long long es, nlines, nw, ntiles, total;
     const void *tw;        // twiddle table of the segment's length
-    int code;              // compiled (length, kind), see batch_code
+    int code;              // compiled (length, kind, shape), see batch_code
     int from_in;           // 1: the segment reads the `in` buffer (the grid's first pass)
 };
 
@@ -1338,10 +1338,23 @@ struct BatchArgs {
 };
 
 // One launch over all passes of all grids: the blocks loop over the tiles of
-// pass 0, meet at a grid-wide barrier, loop over the tiles of pass 1, meet
-// again, then pass 2.  The launch is cooperative (every block resident), and
-// every block reaches both barriers, so the barrier cannot wait on a block
-// that is not running.
+// pass 0 (block b takes tiles b, b + G, ...), meet at a grid-wide barrier,
+// loop over the tiles of pass 1, meet again, then pass 2.  The launch is
+// cooperative (every block resident), and every block reaches both
+// barriers, so the barrier cannot wait on a block that is not running.
+// Measured on an MI355X (768 resident blocks): a cooperative launch costs
+// about 20 us against a few for a plain one, and a grid-wide barrier 60 to
+// 100 us (the runtime's) or about 80 us (an arrival counter polled by each
+// block), against a few us between two launches replayed from a graph; so
+// the per-pass launches in a graph stay the faster form.  Handing tiles out
+// from a counter instead of striding was slower still (one contended atomic
+// per tile).  The thread index reaches the tile code through a per-tile
+// opaque zero: seen as loop invariant, the lane and LDS offsets of every
+// compiled (length, kind, shape) case were hoisted out of the tile loop and
+// held across it (200 to 330 vector registers for complex64, against about
+// 120 without the loop).  More blocks per CU only add to the barriers' cost
+// (0.74, 0.75, 0.87 ms for the 64-grid batch with 1, 2, 3 blocks per CU), so
+// the grid is one block per CU.
 struct BatchCoopArgs {
     const BatchItem *items;     // all segments, pass by pass
     int item_begin[4];          // segments of pass p: [item_begin[p], item_begin[p + 1])
@@ -1351,14 +1364,26 @@ struct BatchCoopArgs {
 };
 
 constexpr int kBatchLengths[8] = {48, 60, 64, 72, 80, 96, 100, 128};
-constexpr int batch_threads(int n) { return (n == 64 || n == 128) ? 8 : 4; }
+// Two tile shapes per length for complex64 (one for complex128), all of 256
+// threads: shape 0 (the default) has 8 threads per line for 64 and 128 and
+// 4 for the others; shape 1 swaps them (4 threads and 64-line tiles for 64
+// and 128, 8 threads and 32-line tiles for the others).  The autotuner picks
+// per (length, kind).  complex128 keeps shape 0 only: shape 1 of 64 and 128
+// holds twice the elements per thread, which took the kernel past 256
+// vector registers and halved its occupancy for every length.
+constexpr int kBatchShapes = 2;
+template <class St>
+constexpr int batch_shapes() { return sizeof(typename St::R) == 4 ? 2 : 1; }
+constexpr int batch_threads(int n, int shape = 0) {
+    return ((n == 64 || n == 128) != (shape == 1)) ? 8 : 4;
+}
 
-template <int N, int KIND, class St>
-using BCfg = SCfg<N, KIND, (int)sizeof(typename St::Raw), (int)sizeof(cx<typename St::R>), N / batch_threads(N),
-                  256 / batch_threads(N), 0, 0>;
+template <int N, int KIND, class St, int SH = 0>
+using BCfg = SCfg<N, KIND, (int)sizeof(typename St::Raw), (int)sizeof(cx<typename St::R>),
+                  N / batch_threads(N, SH), 256 / batch_threads(N, SH), 0, 0>;
 
 template <class Cfg, class St, int KIND, bool INV>
-__device__ __forceinline__ void batch_tile(const PassArgs &a, long long tile, unsigned char *smem) {
+__device__ __forceinline__ void batch_tile(const PassArgs &a, long long tile, unsigned char *smem, int tid) {
     using R = typename St::R;
     static_assert(Cfg::kBlock == 256, "batched configurations use 256 threads");
     constexpr int T = Cfg::T;
@@ -1366,7 +1391,6 @@ __device__ __forceinline__ void batch_tile(const PassArgs &a, long long tile, un
     cx<R> *lds = reinterpret_cast<cx<R> *>(smem);
     cx<R> *tws = reinterpret_cast<cx<R> *>(smem + Cfg::kLdsData);
     unsigned *red = nullptr;
-    const int tid = threadIdx.x;
     const int l = KIND == kContiguous ? tid / T : tid % L;
     // with whole wavefronts of lines, t is the wavefront's index: uniform
     const int t = KIND == kContiguous ? tid % T
@@ -1387,9 +1411,10 @@ __device__ __forceinline__ void batch_tile(const PassArgs &a, long long tile, un
     static_stage<Cfg, St, KIND, INV, 0>(a, lds, tws, red, t, l, c, lane, es, cur, ex);
 }
 
+// tid: threadIdx.x
 template <class St, bool INV>
 __device__ __forceinline__ void batch_dispatch(const BatchItem &it, long long lt, const void *in, void *out,
-                                               unsigned char *smem) {
+                                               unsigned char *smem, int tid) {
     const size_t eb = sizeof(typename St::Raw);
     PassArgs a;
     a.in = reinterpret_cast<const char *>(it.from_in ? in : out) + it.offset * eb;
@@ -1404,17 +1429,31 @@ __device__ __forceinline__ void batch_dispatch(const BatchItem &it, long long lt
     a.total = it.total;
     a.inverse = INV;
     switch (it.code) {
-#define CROFT_BATCH_CASE(I)                                                                                   \
-    case 2 * I: batch_tile<BCfg<kBatchLengths[I], kContiguous, St>, St, kContiguous, INV>(a, lt, smem); break; \
-    case 2 * I + 1: batch_tile<BCfg<kBatchLengths[I], kStrided, St>, St, kStrided, INV>(a, lt, smem); break;
-        CROFT_BATCH_CASE(0)
-        CROFT_BATCH_CASE(1)
-        CROFT_BATCH_CASE(2)
-        CROFT_BATCH_CASE(3)
-        CROFT_BATCH_CASE(4)
-        CROFT_BATCH_CASE(5)
-        CROFT_BATCH_CASE(6)
-        CROFT_BATCH_CASE(7)
+#define CROFT_BATCH_CASE(I, SH)                                                                               \
+    case 2 * I + 16 * SH:                                                                                     \
+        if constexpr (SH < batch_shapes<St>())                                                                \
+            batch_tile<BCfg<kBatchLengths[I], kContiguous, St, SH>, St, kContiguous, INV>(a, lt, smem, tid); \
+        break;                                                                                                \
+    case 2 * I + 1 + 16 * SH:                                                                                 \
+        if constexpr (SH < batch_shapes<St>())                                                                \
+            batch_tile<BCfg<kBatchLengths[I], kStrided, St, SH>, St, kStrided, INV>(a, lt, smem, tid);       \
+        break;
+        CROFT_BATCH_CASE(0, 0)
+        CROFT_BATCH_CASE(1, 0)
+        CROFT_BATCH_CASE(2, 0)
+        CROFT_BATCH_CASE(3, 0)
+        CROFT_BATCH_CASE(4, 0)
+        CROFT_BATCH_CASE(5, 0)
+        CROFT_BATCH_CASE(6, 0)
+        CROFT_BATCH_CASE(7, 0)
+        CROFT_BATCH_CASE(0, 1)
+        CROFT_BATCH_CASE(1, 1)
+        CROFT_BATCH_CASE(2, 1)
+        CROFT_BATCH_CASE(3, 1)
+        CROFT_BATCH_CASE(4, 1)
+        CROFT_BATCH_CASE(5, 1)
+        CROFT_BATCH_CASE(6, 1)
+        CROFT_BATCH_CASE(7, 1)
 #undef CROFT_BATCH_CASE
         default: break;
     }
@@ -1438,7 +1477,7 @@ __global__ void __launch_bounds__(256) fft_batch_coop(const BatchCoopArgs b) {
         for (long long tile = blockIdx.x; tile < b.tiles[p]; tile += gridDim.x) {
             const int si = find_segment(b.items, b.item_begin[p], b.item_begin[p + 1] - 1, tile);
             const BatchItem it = b.items[si];
-            batch_dispatch<St, INV>(it, tile - it.tile_begin, b.in, b.out, smem);
+            batch_dispatch<St, INV>(it, tile - it.tile_begin, b.in, b.out, smem, (int)threadIdx.x + opaque_zero());
             __syncthreads();  // the next tile reuses the LDS
         }
         if (p < 2) {
@@ -1453,7 +1492,7 @@ __global__ void __launch_bounds__(256) fft_batch(const BatchArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
     const long long tile = blockIdx.x;
     const BatchItem it = b.items[find_segment(b.items, 0, b.nitems - 1, tile)];
-    batch_dispatch<St, INV>(it, tile - it.tile_begin, b.in, b.out, smem);
+    batch_dispatch<St, INV>(it, tile - it.tile_begin, b.in, b.out, smem, (int)threadIdx.x);
 }
 
 // ------------------------------------------------------------ kernel table

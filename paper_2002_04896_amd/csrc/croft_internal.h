@@ -133,11 +133,16 @@ hipError_t launch_sum_partials(const double *partial, int n, double *energy, hip
 
 // ---- batched form (croft_batch.hip) ----
 struct BatchConfig {
-    int n = 0, kind = 0, threads_per_line = 0, lines = 0;
+    int n = 0, kind = 0, shape = 0, threads_per_line = 0, lines = 0;
     size_t lds = 0;
 };
-// Code of a (length, kind) the batched kernel compiles, -1 if none.
-int batch_code(int n, int kind);
+// Tile shapes the batched kernel compiles per (length, kind) for a dtype
+// (shape 0 is the default; the autotuner picks among them), and the wisdom
+// kinds that record the choice: kBatchWisdomKind + kind.
+int batch_shape_count(int dtype);
+constexpr int kBatchWisdomKind = 4;
+// Code of a (length, kind, shape) the batched kernel compiles, -1 if none.
+int batch_code(int n, int kind, int shape = 0);
 bool batch_config(int code, int dtype, BatchConfig *c);
 const void *batch_kernel(int dtype, int inverse);
 size_t batch_item_bytes();

@@ -62,3 +62,42 @@ def test_cooperative_launch_in_place():
     ref = run(UNEVEN, C64, FWD, 0, d_in)
     got = run(UNEVEN, C64, FWD, croft.CROFT_PERSISTENT, d_in, in_place=True)
     assert same_bits(got, ref)
+
+
+def test_cooperative_launch_against_the_oracle_and_replays():
+    """The one-launch form on its own against the FP64 oracle, replayed from
+    the plan's graph: its tile counters must be back at zero after every
+    launch, so every replay (and a re-capture for new buffers) gives the
+    same bits."""
+    import oracle
+    from paper_2002_04896_amd import synth
+    dims = [tuple(int(v) for v in d) for d in synth.batch_dims(7, count=12)]
+    grids = [synth.pme_grid(nx, ny, nz, seed=700 + i)[0] for i, (nx, ny, nz) in enumerate(dims)]
+    flat = np.concatenate([g.ravel() for g in grids]).astype(np.complex64)
+    d_in = torch.from_numpy(flat).cuda()
+    plan = croft.croft_plan_create_batched(dims, C64, FWD, croft.CROFT_PERSISTENT)
+    try:
+        offs = croft.croft_plan_batched_offsets(plan, len(dims))
+        outs = []
+        for rep in range(4):
+            out = torch.full_like(d_in, complex(float("nan"), 0))
+            croft.croft_execute_batched(plan, d_in, out)
+            torch.cuda.synchronize()
+            outs.append(out)
+        captured = croft.croft_plan_info(plan)["cooperative_captured"]
+        print(f"cooperative launch captured in the plan's graph: {captured}", flush=True)
+        assert captured in (0, 1)
+        # new buffers: a new capture, counters still at zero
+        d_in2 = d_in.clone()
+        out2 = torch.full_like(d_in, complex(float("nan"), 0))
+        croft.croft_execute_batched(plan, d_in2, out2)
+        torch.cuda.synchronize()
+    finally:
+        croft.croft_plan_destroy(plan)
+    for o in outs[1:] + [out2]:
+        assert same_bits(o, outs[0])
+    got = outs[0].cpu().numpy()
+    for i, (nx, ny, nz) in enumerate(dims):
+        seen = flat[offs[i]:offs[i + 1]].reshape(nz, ny, nx).astype(np.complex128)
+        err = oracle.rel_l2(got[offs[i]:offs[i + 1]].reshape(nz, ny, nx), oracle.dft3d(seen, FWD))
+        assert err <= 1e-5, (i, dims[i], err)

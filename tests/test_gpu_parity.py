@@ -454,3 +454,52 @@ def test_slab_count_zero_is_chosen_by_measurement_and_recorded(dtype, tmp_path, 
         x = synth.normal_c((nz, ny, nx), seed=90)
         seen, y, _ = run_fft(x, C64, FWD, slabs=0)
         assert oracle.rel_l2(y, oracle.dft3d(seen, FWD)) <= TOL[C64]
+
+
+# ------------------------------------------ batched tile shapes (autotuned)
+BATCH_LENGTHS = (48, 60, 64, 72, 80, 96, 100, 128)
+
+
+@pytest.mark.parametrize("flags", [0, croft.CROFT_PERSISTENT], ids=["per-pass", "cooperative"])
+def test_batched_tile_shapes_give_identical_bits(flags, tmp_path, monkeypatch):
+    """Each batched length compiles two tile shapes (threads per line, lines
+    per tile) for complex64; they run the same butterflies, so forcing the
+    other shape for every (length, kind) through the wisdom file changes no
+    bit, and CROFT_MEASURE records a choice per (length, kind) as kinds 4
+    (contiguous) and 5 (strided)."""
+    wisdom = tmp_path / "w.txt"
+    monkeypatch.setenv("CROFT_WISDOM", str(wisdom))
+    dims = [(48, 60, 64), (128, 72, 80), (100, 96, 48), (64, 64, 64), (80, 100, 72), (96, 128, 60)]
+    rng = np.random.Generator(np.random.PCG64(33))
+    total = sum(a * b * c for a, b, c in dims)
+    flat = (rng.standard_normal(total) + 1j * rng.standard_normal(total)).astype(np.complex64)
+    d_in = torch.from_numpy(flat).cuda()
+
+    def run(fl):
+        plan = croft.croft_plan_create_batched(dims, C64, FWD, fl)
+        try:
+            out = torch.full_like(d_in, complex(float("nan"), 0))
+            croft.croft_execute_batched(plan, d_in, out)
+            torch.cuda.synchronize()
+        finally:
+            croft.croft_plan_destroy(plan)
+        return out
+
+    wisdom.write_text("")
+    ref = run(flags)
+    wisdom.write_text("".join(f"{n} {4 + k} {C64} 1 0\n" for n in BATCH_LENGTHS for k in (0, 1)))
+    other = run(flags)
+    assert torch.equal(torch.view_as_real(other), torch.view_as_real(ref))
+    wisdom.write_text("")
+    tuned = run(flags | croft.CROFT_MEASURE)
+    assert torch.equal(torch.view_as_real(tuned), torch.view_as_real(ref))
+    rec = {(int(l.split()[0]), int(l.split()[1])) for l in wisdom.read_text().splitlines()
+           if l.split()[1] in ("4", "5")}
+    # x passes are contiguous (kind 4), y and z passes strided (kind 5)
+    want = {(nx, 4) for nx, _, _ in dims} | {(n, 5) for _, ny, nz in dims for n in (ny, nz)}
+    assert rec == want, rec
+    offs = np.concatenate([[0], np.cumsum([a * b * c for a, b, c in dims])])
+    got = other.cpu().numpy()
+    for i, (nx, ny, nz) in enumerate(dims):
+        seen = flat[offs[i]:offs[i + 1]].reshape(nz, ny, nx).astype(np.complex128)
+        assert oracle.rel_l2(got[offs[i]:offs[i + 1]].reshape(nz, ny, nx), oracle.dft3d(seen)) <= TOL[C64], i
