@@ -345,6 +345,27 @@ def measure_c128(torch, np, croft, pme, steps, checks):
                          "avg_launch_ms": pm[dom]}}
 
 
+def measure_unfused(torch, np, croft, pme, steps, fused_ms):
+    """The paper's Option 2 (no overlap; pack / all-to-all / unpack as
+    separate sweeps, Section 5.1) on one GPU: the unfused plan, whose three
+    FFTs run on contiguous lines with three standalone LDS-tiled transposes
+    of the whole grid, on the same 512^3 PME grid, beside the fused plan."""
+    n = pme.shape[0]
+    N = n ** 3
+    d_in = torch.from_numpy(pme).cuda()
+    d_out = torch.empty_like(d_in)
+    plan = croft.croft_plan_create_ex(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD, croft.CROFT_UNFUSED, 0)
+    ms, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out), steps, 3, 6)
+    croft.croft_plan_destroy(plan)
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    sweep = 2.0 * N * 8
+    return {"ms": ms, "fused_ms": fused_ms, "fusion_speedup": ms / fused_ms,
+            "fft_pass_ms": [pm[0], pm[2], pm[4]], "transpose_ms": [pm[1], pm[3], pm[5]],
+            "transpose_GBps": [sweep / t / 1e6 for t in (pm[1], pm[3], pm[5])],
+            "bytes_moved": 12.0 * N * 8, "effective_GBps_of_moved": 12.0 * N * 8 / ms / 1e6}
+
+
 def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
     """GB/s of a plain device-to-device copy of nbytes (read + write counted)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -692,6 +713,7 @@ def main():
         line["forms"] = measure_real(torch, np, croft, x, max(10, args.steps // 2))
         line["forms"]["convolution"] = measure_conv(torch, np, croft, synth, x, max(10, args.steps // 2))
         line["forms"]["c128_512cube"] = measure_c128(torch, np, croft, x, max(10, args.steps // 2), checks)
+        line["forms"]["option2_unfused_512cube"] = measure_unfused(torch, np, croft, x, max(10, args.steps // 2), ms)
         line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5), checks)
         line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2), checks,
                                            coop=not args.no_coop))

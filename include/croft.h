@@ -89,6 +89,13 @@ enum croft_flags {
     CROFT_MEASURE = 1,        /* time candidate configurations at create (autotune) */
     CROFT_FORCE_GENERIC = 2,  /* use the runtime-radix kernels for every pass */
     CROFT_NO_WISDOM = 4,      /* MEASURE: neither read nor write the wisdom file */
+    CROFT_UNFUSED = 16,       /* croft_plan_create_ex, C64/C128: the paper's Option 2 (Section 5.1,
+                                 no overlap), kept as the measured baseline of the fused passes:
+                                 the three FFTs run on contiguous lines with three standalone
+                                 LDS-tiled transposes of the whole grid between and after them
+                                 (six sweeps instead of three) through a plan-owned work grid;
+                                 same results.  Profiled launches: FFT x, transpose, FFT y,
+                                 transpose, FFT z, transpose (length-1 axes skip their FFT). */
     CROFT_PERSISTENT = 8      /* batched plans: one cooperative launch for every pass of every
                                  grid (all blocks resident, looping over the tiles of pass 0, a
                                  grid-wide barrier, pass 1, a barrier, pass 2) instead

@@ -29,6 +29,7 @@ CROFT_ERR_OUT_OF_MEMORY = 4
 CROFT_ERR_HIP = 5
 CROFT_ERR_INTERNAL = 6
 CROFT_ESTIMATE, CROFT_MEASURE, CROFT_FORCE_GENERIC, CROFT_NO_WISDOM, CROFT_PERSISTENT = 0, 1, 2, 4, 8
+CROFT_UNFUSED = 16
 CROFT_MAX_PASSES = 8
 CROFT_MAX_STAGES = 12
 

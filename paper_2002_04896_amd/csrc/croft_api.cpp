@@ -60,6 +60,10 @@ struct croft_plan {
     bool conv = false;
     double *partial = nullptr;
     long long partial_count = 0;  // doubles in `partial`
+    // unfused schedule (the paper's Option 2): FFT passes on contiguous lines
+    // with standalone transposes between them, through a work grid
+    bool unfused = false;
+    void *uwork = nullptr;
     // slab schedule; slab_auto: K was left to the plan (K = 0 at create)
     bool slab_auto = false;
     hipStream_t side[2] = {nullptr, nullptr};
@@ -226,6 +230,34 @@ int build_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<P
     return CROFT_SUCCESS;
 }
 
+// The pass list of the unfused schedule: along x, y and z in turn, each
+// axis's FFT over contiguous lines of the grid as the preceding transposes
+// leave it (x fastest, then y fastest, then z fastest).  Length-1 axes keep
+// a pass entry that runs nothing.
+int build_unfused_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<PassLaunch> *out) {
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    out->clear();
+    for (int axis = 0; axis < 3; ++axis) {
+        PassLaunch p;
+        p.axis = axis;
+        p.n = dims[axis];
+        p.kind = kContiguous;
+        p.es = 1;
+        p.nlines = N / p.n;
+        p.nw = 1;
+        int cand = 0, waves = 1;
+        wisdom_lookup(p.n, kContiguous, dtype, dir, -1, &cand, &waves);
+        const bool generic = (flags & CROFT_FORCE_GENERIC) != 0 || p.n == 1;
+        if (!select_kernel(p.n, kContiguous, dtype, generic, cand, &p.cfg)) return no_kernel(p.n, dtype);
+        if (!lane_offset_fits(p, dtype) && !select_kernel(p.n, kContiguous, dtype, true, 0, &p.cfg))
+            return no_kernel(p.n, dtype);
+        p.cfg.grid_waves = waves;
+        out->push_back(p);
+    }
+    return CROFT_SUCCESS;
+}
+
 // The pass list of a real transform of an nx x ny x nz real grid (nx even):
 // the real x pass on the half-length complex view, and the complex y and z
 // passes on the (nx/2 + 1) x ny x nz half spectrum.  Forward runs x, y, z;
@@ -375,6 +407,7 @@ void destroy_plan(croft_plan *p) {
     if (p->e1) (void)hipFree(p->e1);
     if (p->e2) (void)hipFree(p->e2);
     if (p->rwork) (void)hipFree(p->rwork);
+    if (p->uwork) (void)hipFree(p->uwork);
     if (p->partial) (void)hipFree(p->partial);
     for (int i = 0; i < 2; ++i) {
         if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
@@ -519,6 +552,15 @@ int attach_resources(croft_plan *p) {
         if ((e = hipMalloc(&p->rwork, bytes)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "real backward work buffer: %s", hipGetErrorString(e));
+        }
+        p->work_bytes += bytes;
+    }
+    if (p->unfused) {
+        const Geometry &g = p->grids[0];
+        const size_t bytes = (size_t)g.nx * g.ny * g.nz * element_bytes(p->dtype);
+        if ((e = hipMalloc(&p->uwork, bytes)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CROFT_ERR_OUT_OF_MEMORY, "unfused work grid: %s", hipGetErrorString(e));
         }
         p->work_bytes += bytes;
     }
@@ -927,10 +969,12 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
     p->passes.resize(grids.size());
     p->real = real || conv;
     p->conv = conv;
+    p->unfused = (flags & CROFT_UNFUSED) != 0;
     for (size_t i = 0; i < grids.size(); ++i) {
-        const int rc = conv   ? build_conv_passes(grids[i], dtype, flags, &p->passes[i])
-                       : real ? build_real_passes(grids[i], dtype, dir, flags, &p->passes[i])
-                              : build_passes(grids[i], dtype, dir, flags, &p->passes[i]);
+        const int rc = conv                         ? build_conv_passes(grids[i], dtype, flags, &p->passes[i])
+                       : real                       ? build_real_passes(grids[i], dtype, dir, flags, &p->passes[i])
+                       : (flags & CROFT_UNFUSED) != 0 ? build_unfused_passes(grids[i], dtype, dir, flags, &p->passes[i])
+                                                      : build_passes(grids[i], dtype, dir, flags, &p->passes[i]);
         if (rc != CROFT_SUCCESS) {
             delete p;
             return nullptr;
@@ -1115,6 +1159,63 @@ int run_slabs(croft_plan *p, const char *in, char *out, const int8_t *in_exp, in
     return CROFT_SUCCESS;
 }
 
+// One standalone transpose (profiled like a pass).
+int run_permute(croft_plan *p, const void *in, void *out, const long long d[3], const long long so[3], int b,
+                hipStream_t s, std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    hipEvent_t a = nullptr, e2 = nullptr;
+    if (prof) {
+        a = pool_event(p);
+        e2 = pool_event(p);
+        if (!a || !e2) return fail(CROFT_ERR_HIP, "profiling event creation failed");
+        (void)hipEventRecord(a, s);
+    }
+    hipError_t e = launch_permute(p->dtype, in, out, d, so, b, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "transpose launch");
+    if (prof) {
+        (void)hipEventRecord(e2, s);
+        prof->push_back({a, e2});
+    }
+    return CROFT_SUCCESS;
+}
+
+// Unfused schedule (the paper's Option 2, Section 5.1): six sweeps.
+//   FFT along x (contiguous)        in   -> work    (x, y, z), x fastest
+//   transpose to y fastest          work -> out     (y, x, z)
+//   FFT along y (contiguous)        out, in place
+//   transpose to z fastest          out  -> work    (z, x, y)
+//   FFT along z (contiguous)        work, in place
+//   transpose back to x fastest     work -> out     (x, y, z)
+// A length-1 axis skips its FFT (the first transpose then reads `in`).
+int run_unfused(croft_plan *p, const char *in, char *out, hipStream_t s,
+                std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof) {
+    const Geometry &g = p->grids[0];
+    const std::vector<PassLaunch> &ps = p->passes[0];
+    const long long nx = g.nx, ny = g.ny, nz = g.nz;
+    char *w = static_cast<char *>(p->uwork);
+    int rc;
+    const char *cur = in;
+    if (ps[0].n > 1) {
+        if ((rc = run_pass(p, ps[0], in, w, nullptr, nullptr, s, prof)) != CROFT_SUCCESS) return rc;
+        cur = w;
+    }
+    {   // (x, y, z) -> (y, x, z): offset y + ny (x + nx z)
+        const long long d[3] = {nx, ny, nz}, so[3] = {ny, 1, ny * nx};
+        if ((rc = run_permute(p, cur, out, d, so, 1, s, prof)) != CROFT_SUCCESS) return rc;
+    }
+    if (ps[1].n > 1 && (rc = run_pass(p, ps[1], out, out, nullptr, nullptr, s, prof)) != CROFT_SUCCESS) return rc;
+    {   // (y, x, z) -> (z, x, y): offset z + nz (x + nx y)
+        const long long d[3] = {ny, nx, nz}, so[3] = {nz * nx, nz, 1};
+        if ((rc = run_permute(p, out, w, d, so, 2, s, prof)) != CROFT_SUCCESS) return rc;
+    }
+    if (ps[2].n > 1 && (rc = run_pass(p, ps[2], w, w, nullptr, nullptr, s, prof)) != CROFT_SUCCESS) return rc;
+    {   // (z, x, y) -> (x, y, z): offset x + nx (y + ny z)
+        const long long d[3] = {nz, nx, ny}, so[3] = {nx * ny, 1, nx};
+        if ((rc = run_permute(p, w, out, d, so, 1, s, prof)) != CROFT_SUCCESS) return rc;
+    }
+    return CROFT_SUCCESS;
+}
+
 // All transforms of a batched plan: one launch per pass for the grids the
 // batched kernel compiles, then the remaining grids with their own launches.
 int run_batch(croft_plan *p, const void *in, void *out, hipStream_t s,
@@ -1203,7 +1304,9 @@ int execute_any(croft_plan *p, const void *in, const int8_t *in_exp, void *out, 
     std::vector<std::pair<hipEvent_t, hipEvent_t>> rec;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> *prof = p->profiling ? &rec : nullptr;
     int rc;
-    if (p->slabs > 1)
+    if (p->unfused)
+        rc = run_unfused(p, (const char *)in, (char *)out, s, prof);
+    else if (p->slabs > 1)
         rc = run_slabs(p, (const char *)in, (char *)out, in_exp, out_exp, s, prof, e1, e2);
     else
         rc = run_grid(p, 0, (const char *)in, (char *)out, in_exp, out_exp, s, prof, e1, e2);
@@ -1281,10 +1384,16 @@ croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, in
     g_last_error.clear();
     if (check_dtype_dir(dtype, dir) != CROFT_SUCCESS) return nullptr;
     if (check_dims(nx, ny, nz) != CROFT_SUCCESS) return nullptr;
-    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
+    if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM | CROFT_UNFUSED)) {
         fail(CROFT_ERR_INVALID_VALUE, "unknown flags 0x%x", flags);
         return nullptr;
     }
+    if ((flags & CROFT_UNFUSED) && (is_half(dtype) || slabs > 1)) {
+        fail(is_half(dtype) ? CROFT_ERR_UNSUPPORTED_DTYPE : CROFT_ERR_INVALID_VALUE,
+             "CROFT_UNFUSED takes CROFT_C64 or CROFT_C128 and the plain schedule (slabs 0 or 1)");
+        return nullptr;
+    }
+    if ((flags & CROFT_UNFUSED) && slabs == 0) slabs = 1;
     if (slabs < 0 || (slabs > 1 && nz % slabs != 0)) {
         fail(CROFT_ERR_INVALID_VALUE, "slab count %d must be 0, 1 or a divisor of nz = %d", slabs, nz);
         return nullptr;

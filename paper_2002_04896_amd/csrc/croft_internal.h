@@ -159,6 +159,14 @@ hipError_t launch_batch_coop(const void *items, const int item_begin[4], const l
 hipError_t launch_batch(const void *items, int nitems, long long tiles, size_t lds, int dtype, int inverse,
                         const void *in, void *out, hipStream_t stream);
 
+// ---- standalone transpose of the unfused schedule (croft_transpose.hip) ----
+// Permute a complex64/complex128 3D array: input element (i0, i1, i2) of
+// dims d (i0 fastest) goes to output offset i0 so[0] + i1 so[1] + i2 so[2];
+// input axis b (1 or 2) must be the output's fastest (so[b] == 1).  Out of
+// place.
+hipError_t launch_permute(int dtype, const void *in, void *out, const long long d[3], const long long so[3], int b,
+                          hipStream_t stream);
+
 // ---- allocation-free half-storage execute (croft_noalloc.hip) ----
 // Bytes of the static per-GPU scratch array that holds the intermediate
 // exponents of croft_execute_scaled_noalloc.

@@ -382,3 +382,10 @@ def test_energy_partials_cover_every_fused_candidate(dims, dt, n, tmp_path, monk
     assert len(counts) == 1, counts                       # independent of the starting candidate
     assert len(set(blocks)) > 1                            # the candidates do differ in block count
     assert counts.pop() >= max(blocks)
+
+
+def test_unfused_schedule_rejects_half_storage_and_slabs():
+    with pytest.raises(ValueError, match="CROFT_UNFUSED"):
+        croft.croft_plan_create_ex(8, 8, 8, croft.CROFT_C16F, croft.CROFT_FORWARD, croft.CROFT_UNFUSED, 1)
+    with pytest.raises(ValueError, match="CROFT_UNFUSED"):
+        croft.croft_plan_create_ex(8, 8, 8, croft.CROFT_C64, croft.CROFT_FORWARD, croft.CROFT_UNFUSED, 4)
