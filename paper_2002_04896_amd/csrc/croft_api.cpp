@@ -214,6 +214,13 @@ int build_passes(const Geometry &g, int dtype, int dir, int flags, std::vector<P
                 }
             }
         }
+        // 16-bit storage: the static contiguous kernels take one input
+        // exponent per line; a contiguous pass whose elements come from
+        // different lines (y with nx = 1, z with nx = ny = 1) runs the
+        // runtime-radix kernel
+        if (half && p.kind == kContiguous && p.em.a3 != 0 && !p.cfg.generic &&
+            !select_kernel(n, p.kind, dtype, true, 0, &p.cfg))
+            return no_kernel(n, dtype);
         out->push_back(p);
     }
     if (out->empty()) {  // 1 x 1 x 1 grid: one length-1 pass copies in to out
@@ -710,6 +717,7 @@ int measure_passes(croft_plan *p) {
     if (rc != CROFT_SUCCESS) return rc;
     for (auto &ps : p->passes)
         for (PassLaunch &pl : ps) {
+            if (pl.cfg.generic) continue;  // a pass the planner sent to the runtime-radix kernel keeps it
             auto it = best.find({pl.n, pl.kind, wisdom_axis(pl.kind, pl.axis)});
             if (it != best.end()) pl.cfg = it->second;
         }

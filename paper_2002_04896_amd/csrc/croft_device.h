@@ -272,6 +272,12 @@ struct StHalf {
     static __device__ __forceinline__ Raw fetch(const void *p, long long i) {
         return reinterpret_cast<const unsigned *>(p)[i];
     }
+    // the stored value itself, unscaled
+    static __device__ __forceinline__ cx<R> decode_raw(Raw u) {
+        const unsigned short lo = static_cast<unsigned short>(u & 0xffffu);
+        const unsigned short hi = static_cast<unsigned short>(u >> 16);
+        return {BF ? bf16_bits_to_float(lo) : f16_bits_to_float(lo), BF ? bf16_bits_to_float(hi) : f16_bits_to_float(hi)};
+    }
     // value = stored * 2^e
     static __device__ __forceinline__ cx<R> decode(Raw u, int e) {
         const unsigned short lo = static_cast<unsigned short>(u & 0xffffu);
@@ -303,6 +309,19 @@ __device__ __forceinline__ int line_exponent(float mx) {
     int E;
     frexpf(mx, &E);  // mx = f 2^E, f in [0.5, 1)
     const int e = E - 15;
+    return e < -128 ? -128 : (e > 127 ? 127 : e);
+}
+
+// The same exponent for a line whose values carry a common factor 2^ein not
+// yet applied: mx is the largest |re|, |im| before the factor.  Scaling by a
+// power of two is exact, so this is line_exponent(mx 2^ein) wherever that
+// product is a normal FP32 value, without forming it.
+__device__ __forceinline__ int line_exponent_scaled(float mx, int ein) {
+    if (!(mx > 0.0f)) return 0;
+    if (!(mx <= 3.402823466e38f)) return 127;
+    int E;
+    frexpf(mx, &E);
+    const int e = E + ein - 15;
     return e < -128 ? -128 : (e > 127 ? 127 : e);
 }
 
@@ -493,7 +512,19 @@ struct Tile {
     using Elem = typename std::conditional<kRaw, typename St::Raw, cx<typename St::R>>::type;
     Elem e[B0][R0];
     int ex[(kRaw && St::kHalf) ? B0 : 1][(kRaw && St::kHalf) ? R0 : 1];
+    int lex = 0;  // line-scaled contiguous passes: the line's input exponent
 };
+
+// 16-bit storage, contiguous lines: every element of a line carries the
+// line's one input exponent (the first pass reads x-lines, exponents per
+// x-line; the planner sends contiguous passes with per-element exponents to
+// the runtime-radix kernel).  The FFT is linear, so the pass transforms the
+// stored values unscaled and folds 2^ein into the output scaling: the
+// element-wise scaling and the per-element exponent loads disappear, and the
+// results are the same bits (scaling by a power of two commutes with every
+// rounding, as long as no value leaves FP32's normal range).
+template <class St, int KIND>
+constexpr bool kLineScaled = St::kHalf && KIND == kContiguous;
 
 struct TileCoord {
     long long q;      // line coordinate of this thread (contiguous: line; strided: p)
@@ -598,6 +629,7 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
     const long long ut = KIND == kContiguous ? 0 : c.tbase;
     gchar *const ib = uniform_gptr(a.in, (c.tbase - ut) * (long long)sizeof(typename St::Raw));
     gchar *const eb = uniform_gptr(ep, 0);
+    if constexpr (kLineScaled<St, KIND>) tl.lex = *(const __attribute__((address_space(1))) int8_t *)(eb + lane_reg(elane));
 #pragma unroll
     for (int b = 0; b < TL::B0; ++b) {
         const int j = t + b * Cfg::T;
@@ -607,12 +639,14 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
                 const long long u = ut + (long long)(b * Cfg::T + q * TL::NB0) * es;
                 const typename St::Raw r = fetch_at<St, Cfg::kNT>(ib, u, lane);
                 int ex = 0;
-                if constexpr (St::kHalf)
+                if constexpr (St::kHalf && !kLineScaled<St, KIND>)
                     ex = *(const __attribute__((address_space(1))) int8_t *)(eb + ea3 * (b * Cfg::T + q * TL::NB0) +
                                                                               lane_reg(elane));
                 if constexpr (TL::kRaw) {
                     tl.e[b][q] = r;
                     if constexpr (St::kHalf) tl.ex[b][q] = ex;
+                } else if constexpr (kLineScaled<St, KIND>) {
+                    tl.e[b][q] = maybe_swap<INV>(St::decode_raw(r));
                 } else {
                     tl.e[b][q] = maybe_swap<INV>(St::decode(r, ex));
                 }
@@ -669,7 +703,9 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
                 if constexpr (S == 0 && (IO & kFromLds)) {
                     v[b][q] = maybe_swap<INV>(lds[lds_index<KIND, LS, PAD>(l, j + q * NB, L)]);
                 } else if constexpr (S == 0) {
-                    if constexpr (Tile<Cfg, St>::kRaw)
+                    if constexpr (Tile<Cfg, St>::kRaw && kLineScaled<St, KIND>)
+                        v[b][q] = maybe_swap<INV>(St::decode_raw(tl.e[b][q]));
+                    else if constexpr (Tile<Cfg, St>::kRaw)
                         v[b][q] = maybe_swap<INV>(St::decode(tl.e[b][q], St::kHalf ? tl.ex[b][q] : 0));
                     else
                         v[b][q] = tl.e[b][q];
@@ -720,15 +756,19 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
                     for (int q = 0; q < RAD; ++q) mx = fmaxf(mx, fmaxf(fabsf(v[b][q].x), fabsf(v[b][q].y)));
                 }
             }
+            float lmx;
             if constexpr (Cfg::kWaveSync) {
                 // the line's T lanes are one aligned group of its wavefront
-                ex = line_exponent(__uint_as_float(lanes_max_u32<T>(__float_as_uint(mx))));
+                lmx = __uint_as_float(lanes_max_u32<T>(__float_as_uint(mx)));
             } else {
                 atomicMax(&red[l], __float_as_uint(mx));
                 stage_sync<Cfg::kWaveSync>();
-                ex = line_exponent(__uint_as_float(red[l]));
+                lmx = __uint_as_float(red[l]);
             }
+            ex = kLineScaled<St, KIND> ? line_exponent_scaled(lmx, tl.lex) : line_exponent(lmx);
             ex_out = ex;
+            // unscaled values: store v 2^(lex - ex)
+            if constexpr (kLineScaled<St, KIND>) ex -= tl.lex;
         }
         if (c.valid) {
             const long long ut = KIND == kContiguous ? 0 : c.tbase;

@@ -39,6 +39,12 @@ const Builtin kBuiltin[] = {
     {512, 0, 0, 3, 0}, {512, 1, 0, 4, 4}, {1024, 0, 0, 3, 0}, {1024, 1, 0, 7, 1}, {32, 2, 0, 0, 0},
     {64, 2, 0, 0, 2}, {64, 3, 0, 0, 2}, {128, 2, 0, 0, 1}, {128, 3, 0, 0, 2}, {256, 2, 0, 0, 0},
     {256, 3, 0, 0, 1}, {512, 3, 0, 0, 2},
+    // complex64 batched tile shapes (kinds 4 and 5: the batched kernel's
+    // contiguous and strided passes; candidate = shape), the majority of six
+    // CROFT_MEASURE runs (both directions) on the 64-grid PME batch; the
+    // lengths not listed keep shape 0
+    {60, 4, 0, 1, 0}, {60, 5, 0, 1, 0}, {64, 4, 0, 1, 0}, {64, 5, 0, 1, 0}, {72, 4, 0, 1, 0}, {72, 5, 0, 1, 0},
+    {80, 4, 0, 1, 0}, {80, 5, 0, 1, 0}, {96, 4, 0, 1, 0}, {96, 5, 0, 1, 0}, {100, 5, 0, 1, 0},
     // complex128
     {32, 0, 1, 0, 4}, {32, 1, 1, 0, 0}, {48, 0, 1, 0, 2}, {48, 1, 1, 0, 4}, {60, 0, 1, 0, 2}, {60, 1, 1, 0, 2},
     {64, 0, 1, 0, 0}, {64, 1, 1, 0, 4}, {72, 0, 1, 0, 1}, {72, 1, 1, 0, 0}, {80, 0, 1, 0, 1}, {80, 1, 1, 0, 0},
