@@ -133,9 +133,13 @@ int no_kernel(int n, int dtype) {
 // a strided pass are not whole lines (a real grid's half-spectrum y pass,
 // 257 complex64 per row: 0.34-0.41 ms with the hint on loads or stores,
 // 0.20 without), a candidate with the hint gives way to its plain twin.
+// Likewise a candidate that runs whole tiles only (the half-tile copy into
+// LDS) gives way to its twin where the last tile of a row is partial.
 void plain_on_partial_lines(const PassLaunch &p, int dtype, KernelConfig *cfg) {
     if (p.kind != kStrided || cfg->generic || cfg->plain < 0) return;
-    if ((p.es * (long long)element_bytes(dtype)) % 128 == 0) return;
+    const bool partial_lines = (p.es * (long long)element_bytes(dtype)) % 128 != 0;
+    const bool partial_tiles = cfg->whole_tiles && p.es % cfg->lines != 0;
+    if (!partial_lines && !partial_tiles) return;
     KernelConfig c;
     if (select_kernel(p.n, p.kind, dtype, false, cfg->plain, &c) && c.candidate == cfg->plain) *cfg = c;
 }

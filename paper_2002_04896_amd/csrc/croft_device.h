@@ -962,7 +962,17 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long n) {
 // NTM: the non-temporal hint on the loads (bit 0) and on the stores (bit 1).
 // REV: with one block per tile, the tiles in reverse order (the pass starts
 // where the previous pass, run forward, stopped writing).
-template <int N, class St, bool INV, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false>
+// PF (persistent grids of whole tiles, es a multiple of L): the stored rows
+// of positions 0 .. N/2 - 1 of the block's next tile are copied into the
+// exchange area (global_load_lds, 16 bytes a lane, no registers held) as
+// soon as the current tile's exchange is done, before its stores; they
+// arrive during the last stage and the stores, and the next tile loads
+// only its other half from global memory.  Issued before the stores, they
+// complete before them (vector memory counts in order), so waiting for
+// them leaves the stores in flight: 64 stores per lane follow them, and a
+// wait for at most 62 outstanding operations covers the copy.
+template <int N, class St, bool INV, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false,
+          bool PF = false>
 __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     using R = typename St::R;
     using C = LanesCfg<N, St, BLOCK>;
@@ -996,11 +1006,43 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     // the position (h for the loads, NB2 h for the stores)
     const unsigned lane_b = (unsigned)(((long long)l + h * es) * (long long)sizeof(typename St::Raw));
     const unsigned lane_s = (unsigned)(((long long)l + (long long)NB2 * h * es) * (long long)sizeof(typename St::Raw));
+    using Raw = typename St::Raw;
+    constexpr int kS = (int)sizeof(Raw);
+    // rows 0 .. N/2 - 1 of tile (ctx, cw) into the exchange area: row p at
+    // byte (p L + line) kS; a wave instruction moves 1 KiB (16 bytes a lane)
+    auto copy_half = [&](long long ctx, long long cw) {
+        constexpr int kRowB = L * kS;
+        static_assert(kRowB >= 16 && 1024 % kRowB == 0, "whole rows per 1 KiB copy");
+        constexpr int kRowsPerI = 1024 / kRowB, kLanesPerRow = 64 / kRowsPerI, kInstr = (N / 2) / kRowsPerI;
+        const int lane = tid & 63;
+        const int wave = (int)__builtin_amdgcn_readfirstlane((unsigned)(tid >> 6));
+        const char *gb = reinterpret_cast<const char *>(a.in) + (ctx * L + cw * es * N) * (long long)kS;
+        const long long rowb = es * (long long)kS;
+        const int rr = lane / kLanesPerRow, cb = (lane % kLanesPerRow) * 16;
+        for (int k = wave; k < kInstr; k += BLOCK / 64) {
+            const char *src = gb + (long long)(k * kRowsPerI + rr) * rowb + cb;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)(smem + (size_t)k * 1024), 16,
+                                             0, 0);
+        }
+    };
+    static_assert(!PF || (size_t)(N / 2) * L * kS <= C::kX, "the copied half fits the exchange area");
+    bool first = true;
+    if constexpr (PF) copy_half(tx, w);
     for (;;) {
         const int tz = opaque_zero();
         const long long q = tx * L + l;  // this lane's line
         const bool valid = q < es;
         const long long tbase = tx * L + w * es * N;
+        if constexpr (PF) {
+            // this wave's copy of the tile's first half is done (the first
+            // tile: nothing else in flight; later: the previous tile's 64
+            // stores per lane followed it), then every wave's
+            if (first) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+            else __builtin_amdgcn_s_waitcnt(0xCF7E);        // vmcnt(62)
+            first = false;
+            __syncthreads();
+        }
         cx<R> v[64];
         if (valid) {
             unsigned elane = 0;
@@ -1023,9 +1065,16 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
 #pragma unroll
             for (int m = 0; m < 64; ++m) {
                 const long long pos0 = t0 + tz + TPL * m;  // uniform part of the position
-                raw[m] = fetch_at<St, (NTM & 1) != 0>(ib, pos0 * est, lane_b);
+                if (!PF || m >= 32)
+                    raw[m] = fetch_at<St, (NTM & 1) != 0>(ib, pos0 * est, lane_b);
                 if constexpr (St::kHalf)
                     ex[m] = *(const __attribute__((address_space(1))) int8_t *)(eb + ea3t * pos0 + lane_reg(elane));
+            }
+            if constexpr (PF) {
+                // positions t + TPL m, m < 32, from the copy in the exchange area
+                const Raw *xr = reinterpret_cast<const Raw *>(smem);
+#pragma unroll
+                for (int m = 0; m < 32; ++m) raw[m] = xr[(t + TPL * m) * L + l];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1077,6 +1126,21 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
                     else y[TPL * u + p].x = e;
                 }
         }
+        // the block's next tile (coordinates as advanced below)
+        const long long nt = tile + G;
+        long long ntx = tx + gx, nw = w + gw;
+        if (ntx >= a.ntiles) {
+            ntx -= a.ntiles;
+            nw += 1;
+        }
+        if constexpr (PF) {
+            if (nt < a.total) {
+                __syncthreads();  // every wave has read its exchange values
+                __builtin_amdgcn_sched_barrier(0);
+                copy_half(ntx, nw);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
         // stage 2: butterfly j = NB2 t + u, twiddles w_N^(p j); outputs j + 64p
         float mx = 0.0f;
 #pragma unroll
@@ -1123,14 +1187,10 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
                 }
             }
         }
-        tile += G;
+        tile = nt;
         if (tile >= a.total) break;
-        tx += gx;
-        w += gw;
-        if (tx >= a.ntiles) {
-            tx -= a.ntiles;
-            w += 1;
-        }
+        tx = ntx;
+        w = nw;
     }
 }
 
@@ -1543,6 +1603,7 @@ struct Entry {
     size_t lds;
     RPlan plan;
     int plain = -1;  // non-temporal candidates: the candidate without the hint
+    bool whole_tiles = false;  // runs only where every tile is whole (es a multiple of L)
 };
 
 // An entry whose kernel uses the non-temporal hint, with the candidate index
@@ -1577,7 +1638,8 @@ Entry make_entry(int cand) {
 }
 
 // The lane-per-line strided configuration of length N (512 or 1024).
-template <int N, class St, int DT, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false>
+template <int N, class St, int DT, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false,
+          bool PF = false>
 Entry make_lanes_entry(int cand) {
     using C = LanesCfg<N, St, BLOCK>;
     static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
@@ -1586,8 +1648,9 @@ Entry make_lanes_entry(int cand) {
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO, REV>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO, REV>);
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO, REV, PF>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO, REV, PF>);
+    e.whole_tiles = PF;
     e.T = C::TPL;
     e.L = C::L;
     e.block = BLOCK;

@@ -18,7 +18,10 @@ namespace dev {
 // (9 non-temporal), 10 and 11 those with an XCD-contiguous tile order (11 non-temporal);
 // 12 and 13 (length 512) 8 with the non-temporal hint on the loads only and on the
 // stores only, 14 is 12 in the XCD-contiguous order, 15 and 16 are 12 and 8 with the
-// tiles in reverse order; at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order; contiguous 3:
+// tiles in reverse order, 17 and 18 are 8 and 9 copying the first half of the next tile into LDS
+// during the current one (whole tiles, persistent grids); at 1024, 8 and 9 are 6 and 7 with the
+// XCD-contiguous order, 10 to 12 are 6 with that copy (non-temporal stores in 11, loads and stores
+// in 12); contiguous 3:
 // non-temporal;
 // fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
 #define CAND(N, EW, LW, EW2, LW2)                                                \
@@ -47,6 +50,11 @@ std::vector<Entry> entries_c64() {
         make_lanes_entry<512, StC64, kC64, 0, 256, false, true>(16),
         make_lanes_entry<1024, StC64, kC64, 0>(6), with_plain(make_lanes_entry<1024, StC64, kC64, 3>(7), 6),
         make_lanes_entry<1024, StC64, kC64, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StC64, kC64, 3, 512, true>(9), 8),
+        with_plain(make_lanes_entry<1024, StC64, kC64, 0, 512, false, false, true>(10), 6),
+        with_plain(make_lanes_entry<1024, StC64, kC64, 2, 512, false, false, true>(11), 6),
+        with_plain(make_lanes_entry<1024, StC64, kC64, 3, 512, false, false, true>(12), 6),
+        with_plain(make_lanes_entry<512, StC64, kC64, 0, 256, false, false, true>(17), 8),
+        with_plain(make_lanes_entry<512, StC64, kC64, 3, 256, false, false, true>(18), 8),
     };
 }
 

@@ -42,7 +42,9 @@ struct KernelConfig {
     const void *func_inv = nullptr;  // the same configuration, inverse direction
     bool generic = false;            // runtime-radix kernel
     int candidate = 0;               // index among the compiled configurations
-    int plain = -1;                  // non-temporal: the candidate without the hint
+    int plain = -1;                  // non-temporal or whole-tile: the candidate to run instead where
+                                     // rows are not whole 128-byte lines or tiles are not whole
+    bool whole_tiles = false;        // needs es to be a multiple of the lines per tile
     int threads_per_line = 0;        // T
     int lines = 0;                   // L, lines per block
     int block = 0;                   // T * L

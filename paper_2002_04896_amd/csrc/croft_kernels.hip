@@ -419,6 +419,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
             cfg->bluestein = 0;
             cfg->candidate = pick->cand;
             cfg->plain = pick->plain;
+            cfg->whole_tiles = pick->whole_tiles;
             cfg->threads_per_line = pick->T;
             cfg->lines = pick->L;
             cfg->block = pick->block;
@@ -450,6 +451,8 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
         cfg->generic = true;
         cfg->bluestein = m;
         cfg->candidate = 0;
+        cfg->plain = -1;
+        cfg->whole_tiles = false;
         cfg->threads_per_line = T;
         cfg->lines = L;
         cfg->block = ((T * L + 63) / 64) * 64;
@@ -483,6 +486,8 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
     cfg->generic = true;
     cfg->bluestein = 0;
     cfg->candidate = 0;
+    cfg->plain = -1;
+    cfg->whole_tiles = false;
     cfg->threads_per_line = T;
     cfg->lines = L;
     cfg->block = ((T * L + 63) / 64) * 64;

@@ -163,14 +163,16 @@ def _describe_with_wisdom(tmp_path, monkeypatch, text, *args):
 def test_builtin_wisdom_picks_one_line_per_lane_at_512(tmp_path, monkeypatch):
     # complex64 strided passes of length 512, both directions: one line per
     # lane (8 threads per line) in 32-line tiles (256-byte rows, 256-thread
-    # blocks, one block per tile) on both axes, the y pass with non-temporal
+    # blocks) on both axes, the y pass one block per tile with non-temporal
     # loads and the tiles in reverse order, the z pass with non-temporal
-    # loads and stores
+    # loads and stores, two waves of resident blocks, copying the next
+    # tile's first half into LDS
     for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
         passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64, direction)
-        assert [p["candidate"] for p in passes][1:] == ["15", "9"]
+        assert [p["candidate"] for p in passes][1:] == ["15", "18"]
         for p in passes[1:]:
-            assert (p["T"], p["L"], p["block"], p["waves"]) == ("8", "32", "256", "0")
+            assert (p["T"], p["L"], p["block"]) == ("8", "32", "256")
+        assert [p["waves"] for p in passes][1:] == ["0", "2"]
     # a wisdom line for any axis comes before the built-in per-axis choices
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 2 1\n", 512, 512, 512)
     assert [p["candidate"] for p in passes][1:] == ["2", "2"]
@@ -190,10 +192,10 @@ def test_non_temporal_candidates_give_way_on_partial_lines(tmp_path, monkeypatch
     # a real grid's half-spectrum y pass has 257 complex64 per row, not whole
     # 128-byte lines: the complex grid's y choice (candidate 15, non-temporal
     # loads) gives way to its plain twin (10); the z rows (257 * 512
-    # elements) are whole lines and keep the non-temporal candidate 9
+    # elements) are whole lines and whole 32-line tiles and keep candidate 18
     monkeypatch.setenv("CROFT_WISDOM", str(tmp_path / "none.txt"))
     passes = parse_describe(croft.croft_plan_describe_real(512, 512, 512))[1]
-    assert [p["candidate"] for p in passes][1:] == ["10", "9"]
+    assert [p["candidate"] for p in passes][1:] == ["10", "18"]
     # the same twin for any non-temporal candidate named in a wisdom file
     for cand, plain in ((7, 6), (9, 8), (11, 10), (12, 8), (13, 8), (14, 10), (15, 10)):
         w = tmp_path / "w.txt"
@@ -210,7 +212,7 @@ def test_wisdom_per_axis_choices(tmp_path, monkeypatch):
     # line per lane, XCD-contiguous tile order) and the z pass (dispatch
     # order)
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64)
-    assert [p["candidate"] for p in passes][1:] == ["15", "9"]
+    assert [p["candidate"] for p in passes][1:] == ["15", "18"]
     # a file line for any axis comes before the built-in per-axis choices ...
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 4 1\n", 512, 512, 512, croft.CROFT_C64)
     assert [p["candidate"] for p in passes][1:] == ["4", "4"]
@@ -389,3 +391,15 @@ def test_unfused_schedule_rejects_half_storage_and_slabs():
         croft.croft_plan_create_ex(8, 8, 8, croft.CROFT_C16F, croft.CROFT_FORWARD, croft.CROFT_UNFUSED, 1)
     with pytest.raises(ValueError, match="CROFT_UNFUSED"):
         croft.croft_plan_create_ex(8, 8, 8, croft.CROFT_C64, croft.CROFT_FORWARD, croft.CROFT_UNFUSED, 4)
+
+
+def test_half_tile_copy_candidates_need_whole_tiles(tmp_path, monkeypatch):
+    # candidates that copy the next tile's first half into LDS run whole
+    # tiles only: with es not a multiple of the tile's lines the planner runs
+    # their twin (complex64 at 512: 17, 18 -> 8; at 1024: 10-12 -> 6)
+    for n, cand, twin, nx in ((512, 17, 8, 40), (512, 18, 8, 48), (1024, 10, 6, 40), (1024, 12, 6, 48)):
+        # es = nx * 21: 840 and 1008, not multiples of 32
+        passes = _describe_with_wisdom(tmp_path, monkeypatch, f"{n} 1 0 {cand} 1 2\n", nx, 21, n)
+        assert passes[2]["candidate"] == str(twin), (n, cand)
+        passes = _describe_with_wisdom(tmp_path, monkeypatch, f"{n} 1 0 {cand} 1 2\n", 64, 20, n)
+        assert passes[2]["candidate"] == str(cand), (n, cand)
