@@ -422,10 +422,20 @@ def measure_configs(torch, np, croft, synth):
         croft.croft_execute_batched(c, x, yc)
     t_c = [one(lambda: croft.croft_execute_batched(c, x, yc)) for _ in range(200)]
     croft.croft_plan_destroy(c)
+    # and replayed from a captured graph
+    c = croft.croft_plan_create_batched([(n, n, n)], croft.CROFT_C64, croft.CROFT_FORWARD,
+                                        croft.CROFT_PERSISTENT | croft.CROFT_GRAPH)
+    yg = torch.empty_like(x)
+    for _ in range(20):
+        croft.croft_execute_batched(c, x, yg)
+    t_g = [one(lambda: croft.croft_execute_batched(c, x, yg)) for _ in range(200)]
+    croft.croft_plan_destroy(c)
     out["c64_32cube"] = {"forward_median_us": 1e3 * float(np.median(t_f)),
                          "inverse_median_us": 1e3 * float(np.median(t_b)),
                          "forward_one_launch_median_us": 1e3 * float(np.median(t_c)),
                          "one_launch_bitwise_equal": bool(torch.equal(yc, y)),
+                         "forward_one_launch_graph_median_us": 1e3 * float(np.median(t_g)),
+                         "one_launch_graph_bitwise_equal": bool(torch.equal(yg, y)),
                          "round_trip_rel_l2": rel_l2_dev(torch, z / n ** 3, x)}
     flush = torch.empty(1 << 27, dtype=torch.float32, device="cuda")  # 512 MiB
     for n in (256, 384):
@@ -583,6 +593,9 @@ def measure_forms(torch, np, croft, synth, steps, checks, only=None, coop=True):
     # tile shapes chosen by the autotuner on this GPU (nothing read or written to a wisdom file)
     d_meas = torch.empty_like(d_in)
     ms_meas, _ = time_batched(croft.CROFT_MEASURE | croft.CROFT_NO_WISDOM, d_meas)
+    # the same launches replayed from a captured graph
+    d_graph = torch.empty_like(d_in)
+    ms_graph, _ = time_batched(croft.CROFT_GRAPH, d_graph)
     if coop:
         d_coop = torch.empty_like(d_in)
         ms_coop, _ = time_batched(croft.CROFT_PERSISTENT, d_coop)
@@ -612,7 +625,9 @@ def measure_forms(torch, np, croft, synth, steps, checks, only=None, coop=True):
                          "plain_calls_ms": ms_plain, "speedup_vs_plain_calls": ms_plain / ms,
                          "bitwise_equal_to_plain_calls": bool(torch.equal(d_out, ref)),
                          "measured_shapes_ms": ms_meas,
-                         "measured_shapes_bitwise_equal": bool(torch.equal(d_meas, d_out))}
+                         "measured_shapes_bitwise_equal": bool(torch.equal(d_meas, d_out)),
+                         "graph_replay_ms": ms_graph,
+                         "graph_replay_bitwise_equal": bool(torch.equal(d_graph, d_out))}
     if coop:
         out["batched_64"]["cooperative_ms"] = ms_coop
         out["batched_64"]["cooperative_bitwise_equal"] = bool(torch.equal(d_coop, d_out))
@@ -638,7 +653,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

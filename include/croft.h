@@ -96,13 +96,18 @@ enum croft_flags {
                                  (six sweeps instead of three) through a plan-owned work grid;
                                  same results.  Profiled launches: FFT x, transpose, FFT y,
                                  transpose, FFT z, transpose (length-1 axes skip their FFT). */
-    CROFT_PERSISTENT = 8      /* batched plans: one cooperative launch for every pass of every
+    CROFT_PERSISTENT = 8,     /* batched plans: one cooperative launch for every pass of every
                                  grid (all blocks resident, looping over the tiles of pass 0, a
                                  grid-wide barrier, pass 1, a barrier, pass 2) instead
-                                 of one launch per pass.  Replayed from the plan's graph like the
-                                 per-pass form (issued directly if the runtime cannot capture a
-                                 cooperative launch: croft_plan_info.cooperative_captured); same
-                                 results bit for bit. */
+                                 of one launch per pass; same results bit for bit. */
+    CROFT_GRAPH = 32          /* batched plans: replay the launches of croft_execute_batched from
+                                 a HIP graph captured on first use for the given (in, out,
+                                 stream) and captured again when they change.  Without it the
+                                 launches are issued directly, which measured faster: the
+                                 replayed graph took about 15 us longer for one 32^3 grid and
+                                 was no faster for 64 grids.  A cooperative launch
+                                 (CROFT_PERSISTENT) the runtime refuses to capture is issued
+                                 directly: croft_plan_info.graph_replay. */
 };
 
 /* Create a plan for one nx x ny x nz transform (the paper's problem statement,
@@ -185,10 +190,10 @@ int croft_plan_batched_offsets(croft_plan_t plan, size_t *elem_offsets);
 
 /* Run every transform of a batched plan (one from croft_plan_create_batched;
  * others give CROFT_ERR_INVALID_VALUE): one launch per axis pass covering
- * all grids, replayed from a HIP graph captured on first use for the given
- * (in, out, stream) -- or, with CROFT_PERSISTENT, one cooperative launch.  Grids
- * whose lengths the batched kernels do not compile (any outside 48, 60, 64,
- * 72, 80, 96, 100, 128) run with launches of their own inside the same graph.
+ * all grids -- or, with CROFT_PERSISTENT, one cooperative launch -- issued on
+ * `stream`, or with CROFT_GRAPH replayed from a HIP graph.  Grids whose lengths
+ * the batched kernels do not compile (any outside 48, 60, 64, 72, 80, 96, 100,
+ * 128) run with launches of their own (inside the same graph with CROFT_GRAPH).
  * Same in/out rules as croft_execute. */
 int croft_execute_batched(croft_plan_t plan, const void *in, void *out, hipStream_t stream);
 
@@ -288,9 +293,11 @@ struct croft_plan_info {
     double flops;             /* sum over grids of 5 N log2 N (real plans: 2.5 N log2 N) */
     int real;                 /* 1 for a plan of croft_plan_create_real or _convolution */
     int convolution;          /* 1 for a plan of croft_plan_create_convolution */
-    int cooperative_captured; /* batched CROFT_PERSISTENT plans: 1 once the cooperative launch
-                                 runs from the plan's graph, 0 if it is issued directly, -1
-                                 before the first execute (and for other plans) */
+    int graph_replay;         /* batched plans: 1 once croft_execute_batched replays a captured
+                                 graph (CROFT_GRAPH), 0 if it issues its launches directly
+                                 (no CROFT_GRAPH, or a cooperative launch that could not be
+                                 captured), -1 before the first execute with CROFT_GRAPH and
+                                 for plans that are not batched */
 };
 int croft_plan_info(croft_plan_t plan, struct croft_plan_info *info);
 

@@ -30,6 +30,7 @@ CROFT_ERR_HIP = 5
 CROFT_ERR_INTERNAL = 6
 CROFT_ESTIMATE, CROFT_MEASURE, CROFT_FORCE_GENERIC, CROFT_NO_WISDOM, CROFT_PERSISTENT = 0, 1, 2, 4, 8
 CROFT_UNFUSED = 16
+CROFT_GRAPH = 32
 CROFT_MAX_PASSES = 8
 CROFT_MAX_STAGES = 12
 
@@ -66,7 +67,7 @@ class PlanInfo(ctypes.Structure):
                 ("elements", ctypes.c_size_t), ("element_bytes", ctypes.c_size_t),
                 ("work_bytes", ctypes.c_size_t), ("algorithmic_bytes", ctypes.c_double),
                 ("flops", ctypes.c_double), ("real", ctypes.c_int), ("convolution", ctypes.c_int),
-                ("cooperative_captured", ctypes.c_int)]
+                ("graph_replay", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pass_"}

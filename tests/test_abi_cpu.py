@@ -26,6 +26,32 @@ def test_library_exports_every_declared_symbol():
     assert sorted(croft.EXPORTED) == names
 
 
+def test_binding_constants_match_the_header():
+    """Every enumerator and integer #define of croft.h has the same value in
+    the Python binding."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {}
+    for body in re.findall(r"enum\s+\w+\s*\{(.*?)\}", text, flags=re.S):
+        for name, val in re.findall(r"(CROFT_\w+)\s*=\s*(\d+)", body):
+            consts[name] = int(val)
+    for m in re.finditer(r"#define\s+(CROFT_\w+)\s+\(?(\d+)u?(?:\s*<<\s*(\d+))?\)?\s*$", text, flags=re.M):
+        consts[m.group(1)] = int(m.group(2)) << int(m.group(3) or 0)
+    assert {"CROFT_GRAPH", "CROFT_PERSISTENT", "CROFT_UNFUSED", "CROFT_C16B", "CROFT_MAX_PASSES",
+            "CROFT_NOALLOC_SCRATCH_BYTES"} <= set(consts)
+    for name, val in consts.items():
+        assert getattr(croft, name) == val, name
+    flags = [consts[k] for k in ("CROFT_MEASURE", "CROFT_FORCE_GENERIC", "CROFT_NO_WISDOM",
+                                 "CROFT_PERSISTENT", "CROFT_UNFUSED", "CROFT_GRAPH")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == len(flags)
+
+
+def test_graph_flag_is_for_batched_plans_only():
+    with pytest.raises(ValueError, match="flags"):
+        croft.croft_plan_create_ex(8, 8, 8, croft.CROFT_C64, -1, croft.CROFT_GRAPH, 1)
+    with pytest.raises(ValueError, match="flags"):
+        croft.croft_plan_create_real(8, 8, 8, croft.CROFT_C64, -1, croft.CROFT_GRAPH)
+
+
 @pytest.mark.parametrize("dims,msg", [
     ((0, 4, 4), "< 1"), ((4, -2, 4), "< 1"), ((4097, 4, 4), "unsupported"),
     ((4, 4, 4097), "unsupported"), ((4, 4, 8192), "unsupported"), ((4, 5000, 4), "unsupported"),

@@ -66,16 +66,15 @@ def test_cooperative_launch_in_place():
 
 def test_cooperative_launch_against_the_oracle_and_replays():
     """The one-launch form on its own against the FP64 oracle, replayed from
-    the plan's graph: its tile counters must be back at zero after every
-    launch, so every replay (and a re-capture for new buffers) gives the
-    same bits."""
+    the plan's graph (CROFT_GRAPH): every replay, and a re-capture for new
+    buffers, gives the same bits."""
     import oracle
     from paper_2002_04896_amd import synth
     dims = [tuple(int(v) for v in d) for d in synth.batch_dims(7, count=12)]
     grids = [synth.pme_grid(nx, ny, nz, seed=700 + i)[0] for i, (nx, ny, nz) in enumerate(dims)]
     flat = np.concatenate([g.ravel() for g in grids]).astype(np.complex64)
     d_in = torch.from_numpy(flat).cuda()
-    plan = croft.croft_plan_create_batched(dims, C64, FWD, croft.CROFT_PERSISTENT)
+    plan = croft.croft_plan_create_batched(dims, C64, FWD, croft.CROFT_PERSISTENT | croft.CROFT_GRAPH)
     try:
         offs = croft.croft_plan_batched_offsets(plan, len(dims))
         outs = []
@@ -84,9 +83,9 @@ def test_cooperative_launch_against_the_oracle_and_replays():
             croft.croft_execute_batched(plan, d_in, out)
             torch.cuda.synchronize()
             outs.append(out)
-        captured = croft.croft_plan_info(plan)["cooperative_captured"]
+        captured = croft.croft_plan_info(plan)["graph_replay"]
         print(f"cooperative launch captured in the plan's graph: {captured}", flush=True)
-        assert captured in (0, 1)
+        assert captured == 1
         # new buffers: a new capture, counters still at zero
         d_in2 = d_in.clone()
         out2 = torch.full_like(d_in, complex(float("nan"), 0))

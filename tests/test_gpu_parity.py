@@ -324,15 +324,18 @@ def test_batched_launch_forms_match_single_grid_plans_bitwise(dtype, direction):
         croft.croft_execute(p, d_in[offs[i]:offs[i + 1]], ref[offs[i]:offs[i + 1]])
         torch.cuda.synchronize()
         croft.croft_plan_destroy(p)
-    for flags in (0, croft.CROFT_PERSISTENT):
+    for flags in (0, croft.CROFT_PERSISTENT, croft.CROFT_GRAPH,
+                  croft.CROFT_PERSISTENT | croft.CROFT_GRAPH):
         plan = croft.croft_plan_create_batched(dims, dtype, direction, flags)
-        for rep in range(3):                     # capture, then replays
+        for rep in range(3):                     # with CROFT_GRAPH: capture, then replays
             out = torch.full_like(d_in, complex(float("nan"), 0))
             croft.croft_execute_batched(plan, d_in, out)
             torch.cuda.synchronize()
             assert torch.equal(out.view(torch.float64 if dtype == C64 else torch.complex128),
                                ref.view(torch.float64 if dtype == C64 else torch.complex128)), (flags, rep)
+        replay = croft.croft_plan_info(plan)["graph_replay"]
         croft.croft_plan_destroy(plan)
+        assert replay == (1 if flags & croft.CROFT_GRAPH else 0), (flags, replay)
     seen = flat[offs[1]:offs[2]].reshape(80, 72, 128).astype(np.complex128)
     got = ref.cpu().numpy()[offs[1]:offs[2]].reshape(80, 72, 128)
     assert oracle.rel_l2(got, oracle.dft3d(seen, direction)) <= TOL[dtype]
@@ -367,7 +370,7 @@ def test_batched_in_place():
     rng = np.random.Generator(np.random.PCG64(32))
     flat = (rng.standard_normal(total) + 1j * rng.standard_normal(total)).astype(np.complex64)
     outs = []
-    for flags in (0, croft.CROFT_PERSISTENT):
+    for flags in (0, croft.CROFT_PERSISTENT, croft.CROFT_GRAPH):
         d = torch.from_numpy(flat).cuda()
         plan = croft.croft_plan_create_batched(dims, C64, FWD, flags)
         croft.croft_execute_batched(plan, d, d)
@@ -375,6 +378,7 @@ def test_batched_in_place():
         croft.croft_plan_destroy(plan)
         outs.append(d.cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
     seen = flat[:64 * 48 * 60].reshape(60, 48, 64).astype(np.complex128)
     assert oracle.rel_l2(outs[0][:64 * 48 * 60].reshape(60, 48, 64), oracle.dft3d(seen)) <= TOL[C64]
 
