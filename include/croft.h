@@ -43,10 +43,13 @@
  * plan per concurrently used stream.  Destroy a plan only after its work has
  * completed.
  *
- * Errors: every call returns a croft_status (create functions return NULL);
- * croft_last_error() then holds a message for the calling thread.  HIP launch
- * errors are reported as CROFT_ERR_HIP with HIP's own message.  No C++
- * exception crosses this boundary.
+ * Errors: every call returns a croft_status (create functions return NULL
+ * and leave it in croft_last_status()); croft_last_error() then holds a
+ * message for the calling thread.  HIP launch errors are reported as
+ * CROFT_ERR_HIP with HIP's own message.  No C++ exception crosses this
+ * boundary.  A failed create frees whatever it had allocated.  For tests, the
+ * environment variable CROFT_TEST_FAIL_ALLOC=k (k >= 1) makes the k-th device
+ * allocation of each plan creation fail as CROFT_ERR_OUT_OF_MEMORY.
  */
 #ifndef CROFT_H
 #define CROFT_H
@@ -175,6 +178,11 @@ int croft_plan_destroy(croft_plan_t plan);
 
 /* Message describing the last failed call on this thread ("" if none). */
 const char *croft_last_error(void);
+
+/* The croft_status of the last failed call on this thread (CROFT_SUCCESS if
+ * none).  Create functions, which return NULL on failure, report their status
+ * here; like the message, it is reset when a create function starts. */
+int croft_last_status(void);
 
 /* Batched form: `count` independent transforms of uneven sizes,
  * dims[3*i + 0..2] = (nx, ny, nz) of grid i.  Grids are packed back to back in

@@ -37,7 +37,7 @@ CROFT_MAX_STAGES = 12
 # every symbol include/croft.h declares
 EXPORTED = (
     "croft_plan_create", "croft_plan_create_ex", "croft_execute", "croft_execute_scaled",
-    "croft_plan_destroy", "croft_last_error", "croft_plan_create_batched",
+    "croft_plan_destroy", "croft_last_error", "croft_last_status", "croft_plan_create_batched",
     "croft_plan_batched_offsets", "croft_execute_batched", "croft_plan_info",
     "croft_plan_describe", "croft_plan_profile", "croft_plan_profile_read",
     "croft_plan_create_real", "croft_plan_describe_real", "croft_plan_create_convolution",
@@ -107,6 +107,8 @@ def load():
     lib.croft_plan_destroy.restype = i
     lib.croft_last_error.argtypes = []
     lib.croft_last_error.restype = ctypes.c_char_p
+    lib.croft_last_status.argtypes = []
+    lib.croft_last_status.restype = i
     lib.croft_plan_create_batched.argtypes = [i, ctypes.POINTER(ctypes.c_int), i, i, i]
     lib.croft_plan_create_batched.restype = p
     lib.croft_plan_batched_offsets.argtypes = [p, ctypes.POINTER(ctypes.c_size_t)]
@@ -149,12 +151,14 @@ def _check(status: int) -> None:
     raise CroftError(f"croft status {status}: {msg}")
 
 
+def croft_last_status() -> int:
+    return load().croft_last_status()
+
+
 def _created(handle):
     if not handle:
-        msg = croft_last_error()
-        if "out of memory" in msg.lower() or "hip" in msg.lower():
-            raise CroftError(msg)
-        raise ValueError(msg)
+        status = croft_last_status()
+        _check(status if status != CROFT_SUCCESS else CROFT_ERR_INTERNAL)
     return handle
 
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -22,6 +23,12 @@ using namespace croft;
 // ------------------------------------------------------------------ errors
 namespace {
 thread_local std::string g_last_error;
+thread_local int g_last_status = CROFT_SUCCESS;
+
+void clear_error() {
+    g_last_error.clear();
+    g_last_status = CROFT_SUCCESS;
+}
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -30,6 +37,7 @@ int fail(int code, const char *fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_last_error = buf;
+    g_last_status = code;
     return code;
 }
 
@@ -85,6 +93,9 @@ struct croft_plan {
     const void *graph_in = nullptr;
     void *graph_out = nullptr;
     hipStream_t graph_stream = nullptr;
+    // CROFT_TEST_FAIL_ALLOC=k: the k-th plan allocation of this create fails
+    int fail_alloc_at = 0;
+    int alloc_count = 0;
     // profiling
     bool profiling = false;
     std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;  // per execute, per pass
@@ -408,6 +419,18 @@ int check_exp_maps(const Geometry &g, const std::vector<PassLaunch> &ps) {
     return CROFT_SUCCESS;
 }
 
+// Device memory owned by a plan.  With CROFT_TEST_FAIL_ALLOC=k in the
+// environment (k >= 1) the k-th such allocation of a plan creation reports
+// hipErrorOutOfMemory without allocating, so tests can drive every
+// out-of-memory path of plan creation and its cleanup from the host.
+hipError_t plan_alloc(croft_plan *p, void **ptr, size_t bytes) {
+    if (p->fail_alloc_at > 0 && ++p->alloc_count == p->fail_alloc_at) {
+        *ptr = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(ptr, bytes);
+}
+
 void destroy_plan(croft_plan *p) {
     if (!p) return;
     for (auto &kv : p->twiddles) (void)hipFree(kv.second);
@@ -478,7 +501,7 @@ int attach_resources(croft_plan *p) {
             twiddles_fp64(n, w.data());
             void *d = nullptr;
             const size_t bytes = (size_t)n * compute_bytes(p->dtype);
-            if ((e = hipMalloc(&d, bytes)) != hipSuccess) {
+            if ((e = plan_alloc(p, &d, bytes)) != hipSuccess) {
                 (void)hipGetLastError();
                 return fail(CROFT_ERR_OUT_OF_MEMORY, "twiddle table: %s", hipGetErrorString(e));
             }
@@ -500,7 +523,7 @@ int attach_resources(croft_plan *p) {
     auto upload = [&](const std::vector<double> &v, void **out) -> int {
         const size_t count = v.size() / 2;
         const size_t bytes = count * compute_bytes(p->dtype);
-        if ((e = hipMalloc(out, bytes)) != hipSuccess) {
+        if ((e = plan_alloc(p, out, bytes)) != hipSuccess) {
             (void)hipGetLastError();
             *out = nullptr;
             return fail(CROFT_ERR_OUT_OF_MEMORY, "Bluestein table: %s", hipGetErrorString(e));
@@ -550,7 +573,7 @@ int attach_resources(croft_plan *p) {
         long long count = 1;
         for (const PassLaunch &pl : p->passes[0])
             if (pl.kind == kConvZ) count = std::max(count, conv_partials_needed(pl, p->dtype));
-        if ((e = hipMalloc((void **)&p->partial, sizeof(double) * (size_t)count)) != hipSuccess) {
+        if ((e = plan_alloc(p, (void **)&p->partial, sizeof(double) * (size_t)count)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "energy partials: %s", hipGetErrorString(e));
         }
@@ -560,7 +583,7 @@ int attach_resources(croft_plan *p) {
     if (p->real && (p->dir == CROFT_BACKWARD || p->conv) && p->passes[0].size() > 1) {
         const Geometry &g = p->grids[0];
         const size_t bytes = ((size_t)g.nx / 2 + 1) * g.ny * g.nz * compute_bytes(p->dtype);
-        if ((e = hipMalloc(&p->rwork, bytes)) != hipSuccess) {
+        if ((e = plan_alloc(p, &p->rwork, bytes)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "real backward work buffer: %s", hipGetErrorString(e));
         }
@@ -569,7 +592,7 @@ int attach_resources(croft_plan *p) {
     if (p->unfused) {
         const Geometry &g = p->grids[0];
         const size_t bytes = (size_t)g.nx * g.ny * g.nz * element_bytes(p->dtype);
-        if ((e = hipMalloc(&p->uwork, bytes)) != hipSuccess) {
+        if ((e = plan_alloc(p, &p->uwork, bytes)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "unfused work grid: %s", hipGetErrorString(e));
         }
@@ -578,7 +601,7 @@ int attach_resources(croft_plan *p) {
     if (is_half(p->dtype)) {
         const Geometry &g = p->grids[0];
         const size_t b1 = (size_t)g.ny * g.nz, b2 = (size_t)g.nx * g.nz;
-        if ((e = hipMalloc(&p->e1, b1)) != hipSuccess || (e = hipMalloc(&p->e2, b2)) != hipSuccess) {
+        if ((e = plan_alloc(p, (void **)&p->e1, b1)) != hipSuccess || (e = plan_alloc(p, (void **)&p->e2, b2)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "exponent scratch: %s", hipGetErrorString(e));
         }
@@ -622,8 +645,8 @@ int measure_passes(croft_plan *p) {
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
     };
-    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess ||
-        hipMalloc((void **)&ei, maxE) != hipSuccess || hipMalloc((void **)&eo, maxE) != hipSuccess) {
+    if (plan_alloc(p, &a, bytes) != hipSuccess || plan_alloc(p, &b, bytes) != hipSuccess ||
+        plan_alloc(p, (void **)&ei, maxE) != hipSuccess || plan_alloc(p, (void **)&eo, maxE) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
         return fail(CROFT_ERR_OUT_OF_MEMORY, "autotune scratch of %zu bytes", 2 * bytes);
@@ -762,8 +785,8 @@ int measure_slabs(croft_plan *p) {
         if (t1) (void)hipEventDestroy(t1);
     };
     if (ks.size() > 1) {
-        if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess ||
-            hipMalloc((void **)&ei, ebytes) != hipSuccess || hipMalloc((void **)&eo, ebytes) != hipSuccess) {
+        if (plan_alloc(p, &a, bytes) != hipSuccess || plan_alloc(p, &b, bytes) != hipSuccess ||
+            plan_alloc(p, (void **)&ei, ebytes) != hipSuccess || plan_alloc(p, (void **)&eo, ebytes) != hipSuccess) {
             (void)hipGetLastError();
             cleanup();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "slab autotune scratch of %zu bytes", 2 * bytes);
@@ -849,7 +872,7 @@ int upload_batch_tables(croft_plan *p) {
     hipError_t e;
     if (!p->bitems) {
         // every shape choice gives the same number of segments
-        if ((e = hipMalloc(&p->bitems, host.size())) != hipSuccess) {
+        if ((e = plan_alloc(p, &p->bitems, host.size())) != hipSuccess) {
             (void)hipGetLastError();
             return fail(CROFT_ERR_OUT_OF_MEMORY, "batch tables: %s", hipGetErrorString(e));
         }
@@ -896,7 +919,7 @@ int measure_batch_shapes(croft_plan *p) {
         if (t1) (void)hipEventDestroy(t1);
     };
     hipError_t e;
-    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+    if (plan_alloc(p, &a, bytes) != hipSuccess || plan_alloc(p, &b, bytes) != hipSuccess) {
         (void)hipGetLastError();
         cleanup();
         return fail(CROFT_ERR_OUT_OF_MEMORY, "batch autotune scratch of %zu bytes", 2 * bytes);
@@ -1003,6 +1026,7 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
         return nullptr;
     }
     p->batched = batched;
+    if (const char *fa = std::getenv("CROFT_TEST_FAIL_ALLOC")) p->fail_alloc_at = std::atoi(fa);
     if (slabs == 0) {
         // K left to the plan: a recorded choice for this grid, else 1;
         // CROFT_MEASURE times every K below
@@ -1013,9 +1037,11 @@ croft_plan *new_plan(const std::vector<Geometry> &grids, int dtype, int dir, int
     if (attach_resources(p) != CROFT_SUCCESS || ((flags & CROFT_MEASURE) && measure_passes(p) != CROFT_SUCCESS) ||
         (p->slab_auto && (flags & CROFT_MEASURE) && measure_slabs(p) != CROFT_SUCCESS) ||
         (p->batched && build_batch_tables(p) != CROFT_SUCCESS)) {
-        std::string msg = g_last_error;
+        const std::string msg = g_last_error;
+        const int status = g_last_status;
         destroy_plan(p);
         g_last_error = msg;
+        g_last_status = status;
         return nullptr;
     }
     return p;
@@ -1330,7 +1356,7 @@ int execute_any(croft_plan *p, const void *in, const int8_t *in_exp, void *out, 
 // mode 0: complex plan, 1: real plan, 2: convolution plan
 int describe_impl(int nx, int ny, int nz, int dtype, int dir, int mode, char *buf, size_t len) {
     const bool real = mode != 0;
-    g_last_error.clear();
+    clear_error();
     int rc = check_dtype_dir(dtype, dir);
     if (rc != CROFT_SUCCESS) return rc;
     rc = real ? check_real_dims(nx, ny, nz, dtype) : check_dims(nx, ny, nz);
@@ -1392,8 +1418,10 @@ extern "C" {
 
 const char *croft_last_error(void) { return g_last_error.c_str(); }
 
+int croft_last_status(void) { return g_last_status; }
+
 croft_plan_t croft_plan_create_ex(int nx, int ny, int nz, int dtype, int dir, int flags, int slabs) {
-    g_last_error.clear();
+    clear_error();
     if (check_dtype_dir(dtype, dir) != CROFT_SUCCESS) return nullptr;
     if (check_dims(nx, ny, nz) != CROFT_SUCCESS) return nullptr;
     if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM | CROFT_UNFUSED)) {
@@ -1434,7 +1462,7 @@ int croft_execute(croft_plan_t p, const void *in, void *out, hipStream_t stream)
 }
 
 croft_plan_t croft_plan_create_convolution(int nx, int ny, int nz, int dtype, int flags) {
-    g_last_error.clear();
+    clear_error();
     if (check_dtype_dir(dtype, CROFT_FORWARD) != CROFT_SUCCESS) return nullptr;
     if (check_real_dims(nx, ny, nz, dtype) != CROFT_SUCCESS) return nullptr;
     if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
@@ -1506,7 +1534,7 @@ int croft_execute_scaled_noalloc(croft_plan_t p, const void *in, const int8_t *i
 }
 
 croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, int dir, int flags) {
-    g_last_error.clear();
+    clear_error();
     if (count < 1 || !dims) {
         fail(CROFT_ERR_INVALID_VALUE, "batched plan needs count >= 1 and dims");
         return nullptr;
@@ -1539,7 +1567,7 @@ croft_plan_t croft_plan_create_batched(int count, const int *dims, int dtype, in
 }
 
 croft_plan_t croft_plan_create_real(int nx, int ny, int nz, int dtype, int dir, int flags) {
-    g_last_error.clear();
+    clear_error();
     if (check_dtype_dir(dtype, dir) != CROFT_SUCCESS) return nullptr;
     if (check_real_dims(nx, ny, nz, dtype) != CROFT_SUCCESS) return nullptr;
     if (flags & ~(CROFT_MEASURE | CROFT_FORCE_GENERIC | CROFT_NO_WISDOM)) {
