@@ -971,12 +971,21 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long n) {
 // complete before them (vector memory counts in order), so waiting for
 // them leaves the stores in flight: 64 stores per lane follow them, and a
 // wait for at most 62 outstanding operations covers the copy.
+// RP (16-bit storage): the block issues its next tile's loads into
+// registers as soon as the current tile is decoded (64 registers of 16-bit
+// pairs), so they are in flight during the butterflies, the exchange and
+// the stores.  The input exponents sit packed four to a register; they are
+// loaded once per block where every tile of the block reads the same ones
+// (whole tiles, the exponent index independent of the plane, and the
+// block's line stride a multiple of the index period: the 512^3 z pass),
+// else once per tile.
 template <int N, class St, bool INV, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false,
-          bool PF = false>
+          bool PF = false, bool RP = false>
 __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     using R = typename St::R;
     using C = LanesCfg<N, St, BLOCK>;
     static_assert(sizeof(R) == 4, "FP32 compute: 64 elements per thread in registers");
+    static_assert(!RP || (St::kHalf && !PF), "register prefetch: 16-bit storage, no LDS copy");
     constexpr int TPL = C::TPL, L = C::L, NB2 = C::NB2;
     constexpr bool kUniform = L == 64;  // a wavefront is one t
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1027,6 +1036,44 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
         }
     };
     static_assert(!PF || (size_t)(N / 2) * L * kS <= C::kX, "the copied half fits the exchange area");
+    // RP: the raw values of the next tile, and the packed input exponents
+    Raw rawn[RP ? 64 : 1];
+    unsigned epk[RP ? 16 : 1];
+    auto issue_loads = [&](long long ctx, long long cw, int tzz) {
+        if (ctx * L + l < es) {
+            gchar *const nb = uniform_gptr(a.in, (ctx * L + cw * es * N) * (long long)kS);
+            const long long est = es + tzz;
+#pragma unroll
+            for (int m = 0; m < 64; ++m)
+                rawn[m] = fetch_at<St, (NTM & 1) != 0>(nb, (t0 + tzz + (long long)TPL * m) * est, lane_b);
+        }
+    };
+    auto load_exponents = [&](long long ctx, long long cw, int tzz) {
+#pragma unroll
+        for (int k = 0; k < (RP ? 16 : 1); ++k) epk[k] = 0;
+        const long long cq = ctx * L + l;
+        if (a.in_exp && cq < es) {
+            const ExpMap &m = a.em;
+            const unsigned el = exp_line_index(m, cq, cw, m.a0, m.a1, m.a2) + (unsigned)m.a3 * (unsigned)h;
+            gchar *const eb = uniform_gptr(a.in_exp, 0);
+            const long long ea3t = m.a3 + tzz;
+#pragma unroll
+            for (int mm = 0; mm < (RP ? 64 : 0); ++mm) {
+                const unsigned b = *(const __attribute__((address_space(1))) uint8_t *)(
+                    eb + ea3t * (t0 + tzz + (long long)TPL * mm) + lane_reg(el));
+                epk[mm >> 2] |= b << (8 * (mm & 3));
+            }
+        }
+    };
+    bool ehoist = true;  // RP: every tile of the block reads the same exponents
+    if constexpr (RP) {
+        const ExpMap &m = a.em;
+        const bool qinv = m.a0 == 0 || ((gx * L) % m.qmod == 0 && (a.ntiles * L) % m.qmod == 0);
+        ehoist = G >= a.total || !a.in_exp ||
+                 (es % L == 0 && m.a1 == 0 && qinv && (m.a2 == 0 || a.total == a.ntiles));
+        issue_loads(tx, w, opaque_zero());
+        load_exponents(tx, w, opaque_zero());
+    }
     bool first = true;
     if constexpr (PF) copy_half(tx, w);
     for (;;) {
@@ -1034,6 +1081,13 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
         const long long q = tx * L + l;  // this lane's line
         const bool valid = q < es;
         const long long tbase = tx * L + w * es * N;
+        // the block's next tile
+        const long long nt = tile + G;
+        long long ntx = tx + gx, nw = w + gw;
+        if (ntx >= a.ntiles) {
+            ntx -= a.ntiles;
+            nw += 1;
+        }
         if constexpr (PF) {
             // this wave's copy of the tile's first half is done (the first
             // tile: nothing else in flight; later: the previous tile's 64
@@ -1044,7 +1098,18 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
             __syncthreads();
         }
         cx<R> v[64];
-        if (valid) {
+        if constexpr (RP) {
+            if (valid) {
+#pragma unroll
+                for (int m = 0; m < 64; ++m)
+                    v[m] = maybe_swap<INV>(St::decode(rawn[m], (int)(int8_t)(epk[m >> 2] >> (8 * (m & 3)))));
+            } else {
+#pragma unroll
+                for (int m = 0; m < 64; ++m) v[m] = {R(0), R(0)};
+            }
+            if (nt < a.total) issue_loads(ntx, nw, tz);
+            __builtin_amdgcn_sched_barrier(0);
+        } else if (valid) {
             unsigned elane = 0;
             long long ea3 = 0;
             const int8_t *ep = &kZeroExponent;
@@ -1126,13 +1191,6 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
                     else y[TPL * u + p].x = e;
                 }
         }
-        // the block's next tile (coordinates as advanced below)
-        const long long nt = tile + G;
-        long long ntx = tx + gx, nw = w + gw;
-        if (ntx >= a.ntiles) {
-            ntx -= a.ntiles;
-            nw += 1;
-        }
         if constexpr (PF) {
             if (nt < a.total) {
                 __syncthreads();  // every wave has read its exchange values
@@ -1186,6 +1244,9 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
                     a.out_exp[exp_line_index(m, q, w, m.b0, m.b1, m.b2)] = (int8_t)ex;
                 }
             }
+        }
+        if constexpr (RP) {
+            if (!ehoist && nt < a.total) load_exponents(ntx, nw, tz);
         }
         tile = nt;
         if (tile >= a.total) break;
@@ -1639,7 +1700,7 @@ Entry make_entry(int cand) {
 
 // The lane-per-line strided configuration of length N (512 or 1024).
 template <int N, class St, int DT, int NTM, int BLOCK = kLanesBlock, bool XO = false, bool REV = false,
-          bool PF = false>
+          bool PF = false, bool RP = false>
 Entry make_lanes_entry(int cand) {
     using C = LanesCfg<N, St, BLOCK>;
     static_assert(C::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
@@ -1648,8 +1709,8 @@ Entry make_lanes_entry(int cand) {
     e.kind = kStrided;
     e.dtype = DT;
     e.cand = cand;
-    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO, REV, PF>);
-    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO, REV, PF>);
+    e.func[0] = reinterpret_cast<const void *>(&fft_lanes<N, St, false, NTM, BLOCK, XO, REV, PF, RP>);
+    e.func[1] = reinterpret_cast<const void *>(&fft_lanes<N, St, true, NTM, BLOCK, XO, REV, PF, RP>);
     e.whole_tiles = PF;
     e.T = C::TPL;
     e.L = C::L;

@@ -1,10 +1,12 @@
-"""The strided candidates that copy the first half of their next tile into
-LDS while the current tile finishes (global_load_lds; persistent grids of
-whole tiles).  They run the same butterflies as the other candidates of
-their length, so forcing one through the wisdom file must give the default
-plan's bits; the grids are large enough that every block runs several
-tiles (so the copy of a next tile really happens), and the first is also
-checked against exact oracle lines."""
+"""The strided candidates that fetch their next tile while the current one
+finishes: into LDS (the first half, global_load_lds; persistent grids of
+whole tiles) or, for 16-bit storage, into registers (with the input
+exponents packed four to a register, loaded once per block where every
+tile of the block shares them).  They run the same butterflies as the other
+candidates of their length, so forcing one through the wisdom file must
+give the default plan's bits; the grids are large enough that every block
+runs several tiles (so the fetch of a next tile really happens), and the
+first is also checked against exact oracle lines."""
 import numpy as np
 import pytest
 import torch
@@ -27,6 +29,14 @@ CASES = [
     (F16, (512, 128, 256), 2, 512, (17, 18)),
     (BF16, (512, 128, 256), 2, 512, (17, 18)),
     (F16, (1024, 128, 128), 2, 1024, (10, 11)),
+    # register prefetch: exponents once per block (z, nx = 256), once per
+    # tile (z, nx = 100: the block's line stride is no multiple of nx; the
+    # y pass: the exponents change with the plane), partial tiles (es = 2100)
+    (F16, (512, 128, 256), 2, 512, (19, 20)),
+    (BF16, (512, 128, 256), 2, 512, (19, 20)),
+    (F16, (512, 64, 100), 2, 512, (19, 20)),
+    (BF16, (512, 21, 100), 2, 512, (19, 20)),
+    (F16, (128, 512, 256), 1, 512, (19, 20)),
 ]
 
 
@@ -48,7 +58,7 @@ def run(dtype, shape, direction, d_in, e_in):
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
-def test_half_tile_copy_candidates_give_identical_bits(case, tmp_path, monkeypatch):
+def test_next_tile_fetch_candidates_give_identical_bits(case, tmp_path, monkeypatch):
     dtype, shape, axis, n, cands = CASES[case]
     nz, ny, nx = shape
     wisdom = tmp_path / "w.txt"
@@ -60,7 +70,7 @@ def test_half_tile_copy_candidates_give_identical_bits(case, tmp_path, monkeypat
         e_in = None
     else:
         d_in = torch.from_numpy(rng.standard_normal(shape + (2,)).astype(np.float32)).cuda().to(HALF_TORCH[dtype])
-        e_in = torch.zeros((nz, ny), dtype=torch.int8, device="cuda")
+        e_in = torch.from_numpy(rng.integers(-4, 5, size=(nz, ny)).astype(np.int8)).cuda()
     for direction in (FWD, BWD):
         wisdom.write_text(f"{n} 1 {dtype} 6 1 {axis}\n")      # a candidate without the copy
         ref, ref_e, _ = run(dtype, shape, direction, d_in, e_in)
