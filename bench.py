@@ -369,6 +369,33 @@ def measure_c128(torch, np, croft, pme, steps, checks):
                          "avg_launch_ms": pm[dom]}}
 
 
+def measure_bluestein(torch, np, croft, synth, steps, checks, smooth_ms):
+    """Lengths with a large prime factor (Bluestein's algorithm): a forward
+    509^3 complex64 transform (509 is prime; every axis runs as a chirp-
+    multiplied convolution of length 1024 held in LDS), N(0,1) input, next to
+    the 512^3 transform of nearly the same size."""
+    n = 509
+    N = n ** 3
+    x = synth.normal_c((n, n, n), seed=6).astype(np.complex64)
+    d_in = torch.from_numpy(x).cuda()
+    d_out = torch.empty_like(d_in)
+    plan = croft.croft_plan_create(n, n, n, croft.CROFT_C64, croft.CROFT_FORWARD)
+    info = croft.croft_plan_info(plan)
+    ms, pm, _ = time_plan(torch, croft, plan, lambda: croft.croft_execute(plan, d_in, d_out), steps, 3, 3)
+    croft.croft_plan_destroy(plan)
+    kyz = sample_pairs(n, n, 8, seed=16)
+    got = device_lines(d_out, kyz)
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    checks.append({"name": "bluestein_509cube", "compute": lambda o: (got, o.dft3d_lines(x, kyz, -1)),
+                   "tol": 1e-5, "lines": len(kyz), "what": "exact oracle lines of the 509^3 transform"})
+    return {"ms": ms, "GFLOPs": flops_5nlogn(N) / ms / 1e6,
+            "effective_GBps": info["algorithmic_bytes"] / ms / 1e6,
+            "effective_frac_of_8TBps": info["algorithmic_bytes"] / ms / 1e6 / HBM_PEAK_GBPS, "pass_ms": pm,
+            "bluestein_length": info["passes"][0]["bluestein"],
+            "c64_512cube_ms": smooth_ms, "time_vs_512cube": ms / smooth_ms}
+
+
 def measure_unfused(torch, np, croft, pme, steps, fused_ms):
     """The paper's Option 2 (no overlap; pack / all-to-all / unpack as
     separate sweeps, Section 5.1) on one GPU: the unfused plan, whose three
@@ -760,6 +787,8 @@ def main():
         line["forms"]["convolution"] = measure_conv(torch, np, croft, synth, x, max(10, args.steps // 2))
         line["forms"]["c128_512cube"] = measure_c128(torch, np, croft, x, max(10, args.steps // 2), checks)
         line["forms"]["option2_unfused_512cube"] = measure_unfused(torch, np, croft, x, max(10, args.steps // 2), ms)
+        line["forms"]["bluestein_509cube"] = measure_bluestein(torch, np, croft, synth, max(10, args.steps // 2),
+                                                               checks, ms)
         line["forms"]["c64_1024cube"] = measure_large(torch, np, croft, x, max(5, args.steps // 5), checks)
         line["forms"].update(measure_forms(torch, np, croft, synth, max(10, args.steps // 2), checks,
                                            coop=not args.no_coop))

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["croft_entries_c64.hip", "croft_entries_c128.hip", "croft_entries_c16f.hip",
-           "croft_entries_c16b.hip", "croft_kernels.hip", "croft_batch.hip", "croft_noalloc.hip", "croft_transpose.hip", "croft_plan.cpp", "croft_api.cpp",
+           "croft_entries_c16b.hip", "croft_kernels.hip", "croft_batch.hip", "croft_bluestein.hip", "croft_noalloc.hip", "croft_transpose.hip", "croft_plan.cpp", "croft_api.cpp",
            "croft_tune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -207,5 +207,15 @@ void round_to_fp32(const double *in, size_t count, float *out);
 void bluestein_tables_fp64(int n, int m, double *chirp, double *bhat);
 // Smallest power of two >= 2n - 1.
 int bluestein_length(int n);
+// The Bluestein kernel of a pass kind and dtype whose convolution has length
+// m (a power of two, 16 .. 8192) with its launch shape: T threads per line,
+// L lines per block, LDS bytes; func is NULL for any other m and where two
+// line buffers do not fit in LDS (FP64 at 8192).
+struct BluesteinLaunch {
+    const void *func = nullptr;
+    int T = 0, L = 0;
+    size_t lds = 0;
+};
+BluesteinLaunch bluestein_kernel(int kind, int dtype, int m);
 
 }  // namespace croft

@@ -165,108 +165,6 @@ __device__ cx<R> *run_stages(const PassArgs &a, cx<R> *src, cx<R> *dst, const cx
     return src;
 }
 
-// ------------------------------------------------------------ Bluestein
-// Lengths with a prime factor above 5 (Bluestein 1970): with
-// c[j] = exp(-pi i j^2 / n),
-//   X[k] = c[k] sum_j (x[j] c[j]) conj(c[k - j]),
-// a circular convolution of length m (a power of two >= 2n - 1) done as
-// m-point FFTs in LDS: forward FFT of the chirped, zero-padded line, product
-// with the kernel's DFT (precomputed, divided by m), then the inverse FFT as
-// swap(DFT(swap(.))) and the final chirp.  a.S / a.radix / a.tw describe
-// the m-point FFT.  Same line geometry, exponents and inverse-by-swap as the
-// runtime-radix kernel.
-template <class St, int KIND>
-__global__ void __launch_bounds__(256) fft_bluestein(const PassArgs a) {
-    using R = typename St::R;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = a.n, m = a.m, T = a.T, L = a.L;
-    cx<R> *buf0 = reinterpret_cast<cx<R> *>(smem);
-    cx<R> *buf1 = buf0 + (size_t)L * m;
-    unsigned *red = reinterpret_cast<unsigned *>(buf1 + (size_t)L * m);
-    const cx<R> *tw = reinterpret_cast<const cx<R> *>(a.tw);
-    const cx<R> *ch = reinterpret_cast<const cx<R> *>(a.chirp);
-    const cx<R> *bh = reinterpret_cast<const cx<R> *>(a.bhat);
-    const int tid = threadIdx.x;
-    const int l = KIND == kContiguous ? tid / T : tid % L;
-    const int t = KIND == kContiguous ? tid % T : tid / L;
-    const bool active = tid < T * L;
-    long long q, w;
-    if (KIND == kContiguous) {
-        q = (long long)blockIdx.x * L + l;
-        w = 0;
-    } else {
-        q = ((long long)blockIdx.x % a.ntiles) * L + l;
-        w = (long long)blockIdx.x / a.ntiles;
-    }
-    const bool valid = active && q < (KIND == kContiguous ? a.nlines : a.es);
-    const long long es = KIND == kContiguous ? 1 : a.es;
-    const long long base = KIND == kContiguous ? q * n : q + w * a.es * n;
-    const bool inv = a.inverse != 0;
-    int ebase = 0;
-    if constexpr (St::kHalf) {
-        const ExpMap &mp = a.em;
-        ebase = (int)exp_line_index(mp, q, w, mp.a0, mp.a1, mp.a2);
-        if (active && t == 0) red[l] = 0u;
-    }
-    // chirped line, zero-padded to m
-    if (active) {
-        for (int e = t; e < m; e += T) {
-            cx<R> v = {R(0), R(0)};
-            if (valid && e < n) {
-                int ex = 0;
-                if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + a.em.a3 * e] : 0;
-                v = St::decode(St::fetch(a.in, base + es * e), ex);
-                if (inv) v = {v.y, v.x};
-                v = cmul(v, ch[e]);
-            }
-            buf0[glds<KIND>(l, e, m, L)] = v;
-        }
-    }
-    __syncthreads();
-    cx<R> *r = run_stages<R, KIND>(a, buf0, buf1, tw, m, L, l, t, T, active);
-    // product with the kernel's DFT, swapped: the next forward FFT then gives
-    // the unnormalised inverse once swapped back
-    if (active) {
-        for (int e = t; e < m; e += T) {
-            cx<R> &v = r[glds<KIND>(l, e, m, L)];
-            const cx<R> p = cmul(v, bh[e]);
-            v = {p.y, p.x};
-        }
-    }
-    __syncthreads();
-    cx<R> *o = run_stages<R, KIND>(a, r, r == buf0 ? buf1 : buf0, tw, m, L, l, t, T, active);
-    // X[k] = c[k] swap(o[k]); every thread rewrites only the entries it reads later
-    if (active) {
-        for (int e = t; e < n; e += T) {
-            cx<R> &v = o[glds<KIND>(l, e, m, L)];
-            v = cmul(cx<R>{v.y, v.x}, ch[e]);
-        }
-    }
-    int ex = 0;
-    if constexpr (St::kHalf) {
-        float mx = 0.0f;
-        if (active)
-            for (int e = t; e < n; e += T) {
-                const cx<R> v = o[glds<KIND>(l, e, m, L)];
-                mx = fmaxf(mx, fmaxf(fabsf((float)v.x), fabsf((float)v.y)));
-            }
-        if (active) atomicMax(&red[l], __float_as_uint(mx));
-        __syncthreads();
-        if (active) ex = line_exponent(__uint_as_float(red[l]));
-        if (valid && t == 0 && a.out_exp) {
-            const ExpMap &mp = a.em;
-            a.out_exp[exp_line_index(mp, q, w, mp.b0, mp.b1, mp.b2)] = (int8_t)ex;
-        }
-    }
-    if (valid) {
-        for (int e = t; e < n; e += T) {
-            cx<R> v = o[glds<KIND>(l, e, m, L)];
-            if (inv) v = {v.y, v.x};
-            St::store(a.out, base + es * e, v, ex);
-        }
-    }
-}
-
 // ------------------------------------------------------ fused multiply (any length)
 // The fused forward FFT / multiply / inverse FFT pass of a convolution plan for
 // 2^a 3^b 5^c lengths without a compiled fused kernel: strided lines, one tile
@@ -329,23 +227,6 @@ __global__ void __launch_bounds__(256) fft_generic_conv(const PassArgs a) {
         __syncthreads();
     }
     if (tid == 0) a.partial[blockIdx.x] = sum[0];
-}
-
-const void *bluestein_func(int kind, int dtype) {
-    if (kind == kContiguous) {
-        switch (dtype) {
-            case kC64: return reinterpret_cast<const void *>(&fft_bluestein<StC64, kContiguous>);
-            case kC128: return reinterpret_cast<const void *>(&fft_bluestein<StC128, kContiguous>);
-            case kC16F: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<false>, kContiguous>);
-            default: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<true>, kContiguous>);
-        }
-    }
-    switch (dtype) {
-        case kC64: return reinterpret_cast<const void *>(&fft_bluestein<StC64, kStrided>);
-        case kC128: return reinterpret_cast<const void *>(&fft_bluestein<StC128, kStrided>);
-        case kC16F: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<false>, kStrided>);
-        default: return reinterpret_cast<const void *>(&fft_bluestein<StHalf<true>, kStrided>);
-    }
 }
 
 const std::vector<Entry> &table() {
@@ -432,22 +313,13 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
     if (kind == kRealX || kind == kConvZ) return false;  // compiled configurations only
     const int cb = dtype == kC128 ? 16 : 8;                      // compute bytes
     if (make_rplan(n).S < 0) {
-        // Bluestein: two LDS lines of the m-point convolution per line
+        // Bluestein: the kernel compiled for the convolution length m
         const int m = bluestein_length(n);
         const RPlan pm = make_rplan(m);
-        const size_t per_line = 2 * (size_t)m * cb + 4;
-        int lds_lines = (int)((160 * 1024) / per_line);
-        if (lds_lines < 1 || pm.S < 0) return false;
-        int T = m / pm.rmax;
-        if (T > 256) T = 256;
-        if (T < 1) T = 1;
-        int L = kind == kContiguous ? 256 / T : std::max(1, std::min(256 / T, 128 / (int)element_bytes(dtype)));
-        if (L > lds_lines) L = lds_lines;
-        if (L < 1) L = 1;
-        int p2 = 1;
-        while (p2 * 2 <= L) p2 *= 2;
-        L = p2;
-        cfg->func = cfg->func_inv = bluestein_func(kind, dtype);
+        const BluesteinLaunch bl = bluestein_kernel(kind, dtype, m);
+        if (!bl.func || pm.S < 0) return false;
+        const int T = bl.T, L = bl.L;
+        cfg->func = cfg->func_inv = bl.func;
         cfg->generic = true;
         cfg->bluestein = m;
         cfg->candidate = 0;
@@ -456,7 +328,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
         cfg->threads_per_line = T;
         cfg->lines = L;
         cfg->block = ((T * L + 63) / 64) * 64;
-        cfg->lds = (size_t)L * per_line;
+        cfg->lds = bl.lds;
         cfg->nstages = pm.S;
         for (int s = 0; s < pm.S; ++s) cfg->radix[s] = pm.r[s];
         return true;

@@ -17,8 +17,11 @@ C64, C128, F16, BF16 = croft.CROFT_C64, croft.CROFT_C128, croft.CROFT_C16F, crof
 FWD, BWD = croft.CROFT_FORWARD, croft.CROFT_BACKWARD
 
 # (nx, ny, nz): primes on x (contiguous), on y and z (strided), a long prime,
-# and prime lengths mixed with the compiled ones
-SHAPES = [(7, 11, 13), (97, 9, 5), (1009, 3, 2), (17, 256, 19), (128, 131, 2), (60, 7, 64), (2039, 3, 2)]
+# and prime lengths mixed with the compiled ones; together they use every
+# convolution length the kernel is compiled for up to 4096 (16 .. 4096:
+# 7, 11, 17, 41, 97, 131, 509, 1009, 2039)
+SHAPES = [(7, 11, 13), (97, 9, 5), (1009, 3, 2), (17, 256, 19), (128, 131, 2), (60, 7, 64), (2039, 3, 2),
+          (41, 37, 43), (509, 4, 3), (6, 509, 2)]
 
 
 @pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
