@@ -136,8 +136,11 @@ __global__ void __launch_bounds__(256) fft_bluestein(const PassArgs a) {
         q = (long long)blockIdx.x * L + l;
         w = 0;
     } else {
-        q = ((long long)blockIdx.x % a.ntiles) * L + l;
-        w = (long long)blockIdx.x / a.ntiles;
+        // each XCD takes a contiguous run of tiles: the 32-byte rows of
+        // neighbouring tiles share 128-byte lines, which then meet in one L2
+        const long long b = xcd_tile(blockIdx.x, gridDim.x);
+        q = (b % a.ntiles) * L + l;
+        w = b / a.ntiles;
     }
     const bool valid = active && q < (KIND == kContiguous ? a.nlines : a.es);
     const long long es = KIND == kContiguous ? 1 : a.es;
