@@ -61,15 +61,25 @@ def test_create_rejects_bad_sizes(dims, msg):
         croft.croft_plan_create(*dims)
 
 
-@pytest.mark.parametrize("n", [7, 11, 13, 14, 97, 1009, 2039, 4093])
+# one prime for every convolution length the Bluestein kernel is compiled
+# for (16 .. 8192), and 13, 14 (a prime factor times a power of two)
+@pytest.mark.parametrize("n", [7, 11, 13, 14, 17, 41, 97, 131, 509, 1009, 2039, 4093])
 def test_lengths_with_large_prime_factors_use_bluestein(n):
     _, passes = parse_describe(croft.croft_plan_describe(n, 6, 5))
     p = passes[0]
     m = int(p["bluestein"])
     assert p["kernel"] == "bluestein" and m >= 2 * n - 1 and m & (m - 1) == 0 and m < 4 * n
     assert int(p["lds"]) <= 160 * 1024 and int(p["block"]) <= 256
-    _, passes = parse_describe(croft.croft_plan_describe(6, n, 5, croft.CROFT_C16F))
-    assert passes[1]["kernel"] == "bluestein"
+    # every geometry and dtype has a compiled kernel for m, and its launch fits
+    for dt in (croft.CROFT_C64, croft.CROFT_C128, croft.CROFT_C16F, croft.CROFT_C16B):
+        if dt == croft.CROFT_C128 and m > 4096:
+            continue
+        _, contiguous = parse_describe(croft.croft_plan_describe(n, 3, 2, dt))
+        _, strided = parse_describe(croft.croft_plan_describe(2, n, 3, dt))
+        for q in (contiguous[0], strided[1]):
+            assert q["kernel"] == "bluestein" and int(q["bluestein"]) == m, (dt, q)
+            T, L = int(q["T"]), int(q["L"])
+            assert T * L <= int(q["block"]) <= 256 and int(q["lds"]) <= 160 * 1024, (dt, q)
 
 
 def test_bluestein_complex128_limit():
