@@ -105,7 +105,11 @@ enum croft_flags {
                                  of one launch per pass; same results bit for bit. */
     CROFT_GRAPH = 32          /* batched plans: replay the launches of croft_execute_batched from
                                  a HIP graph captured on first use for the given (in, out,
-                                 stream) and captured again when they change.  Without it the
+                                 stream) and captured again when they change; such a capture
+                                 creates a stream and instantiates a graph inside that execute
+                                 (host and driver allocations), later replays allocate
+                                 nothing, and the call cannot itself be captured by the
+                                 caller.  Without it the
                                  launches are issued directly, which measured faster: the
                                  replayed graph took about 15 us longer for one 32^3 grid and
                                  was no faster for 64 grids.  A cooperative launch
