@@ -37,8 +37,9 @@
  * Streams and concurrency: execute calls are asynchronous and ordered on the
  * given stream (NULL = the null stream); they do not synchronise the host,
  * allocate, or copy, except where an entry point says otherwise, so a caller
- * may capture croft_execute and croft_execute_convolution into a HIP graph
- * (not while per-pass profiling is enabled).  One execute
+ * may capture croft_execute, croft_execute_convolution and (for plans made
+ * without CROFT_GRAPH) croft_execute_batched into a HIP graph (not while
+ * per-pass profiling is enabled).  One execute
  * may be in flight per plan at a time (plans hold per-call scratch): use one
  * plan per concurrently used stream.  Destroy a plan only after its work has
  * completed.

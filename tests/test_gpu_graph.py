@@ -1,4 +1,5 @@
-"""croft_execute and croft_execute_convolution under HIP graph capture.
+"""croft_execute, croft_execute_convolution and croft_execute_batched under
+HIP graph capture.
 
 The execute calls launch kernels only (no allocation, copy or host
 synchronisation), so a caller may capture them.  Each test captures one call
@@ -108,6 +109,37 @@ def test_convolution_capture_with_energy():
             graph.replay()
             torch.cuda.synchronize()
             assert torch.equal(out, ref) and torch.equal(e, ref_e), f"replay {rep}"
+    finally:
+        torch.cuda.synchronize()
+        croft.croft_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("flags", [0, croft.CROFT_PERSISTENT], ids=["per-pass", "cooperative"])
+def test_batched_plan_capture(flags):
+    """Without CROFT_GRAPH a batched plan issues its launches directly (one
+    per pass, or one cooperative launch, plus the own launches of a grid the
+    batched kernels do not compile), so a caller may capture the call."""
+    dims = [(48, 60, 64), (64, 64, 64), (45, 27, 2)]
+    total = sum(a * b * c for a, b, c in dims)
+    rng = np.random.Generator(np.random.PCG64(74))
+    x = torch.from_numpy((rng.standard_normal(total) + 1j * rng.standard_normal(total)).astype(np.complex64)).cuda()
+    ref = torch.empty_like(x)
+    out = torch.empty_like(x)
+    plan = croft.croft_plan_create_batched(dims, C64, FWD, flags)
+    try:
+        croft.croft_execute_batched(plan, x, ref)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            croft.croft_execute_batched(plan, x, out)  # warm-up on the capture stream
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            croft.croft_execute_batched(plan, x, out)
+        replay_and_check(g, out, ref, noise_fn())
+        assert croft.croft_plan_info(plan)["graph_replay"] == 0
     finally:
         torch.cuda.synchronize()
         croft.croft_plan_destroy(plan)
