@@ -456,11 +456,13 @@ constexpr int kLdsLimit = 80 * 1024;
 //   PAD: contiguous lines only: one padding element per 32 in LDS.
 //   PF: prefetch the next tile's loads while transforming the current one.
 //   NT: global loads and stores carry the non-temporal (streaming) hint.
+//   XO: with one block per tile, each XCD takes a contiguous run of tiles.
 template <int N, int KIND, int STORE_BYTES, int COMPUTE_BYTES, int EPT = 0, int LREQ = 0, int PAD = 0,
-          int PF = 1, int NT = 0>
+          int PF = 1, int NT = 0, int XO = 0>
 struct SCfg {
     static constexpr bool kPrefetch = PF != 0;
     static constexpr bool kNT = NT != 0;
+    static constexpr bool kXO = XO != 0;
     static constexpr RPlan plan = make_rplan(N);
     static constexpr int S = plan.S;
     static constexpr int kEpt = EPT > 0 ? EPT : plan.rmax;
@@ -820,6 +822,16 @@ __device__ __forceinline__ int tw_source(int i) {
     return src;
 }
 
+// With one block per tile, workgroup b runs on XCD b mod 8 (the dispatcher
+// deals workgroups to the 8 XCDs in turn); this order gives each XCD one
+// contiguous run of tiles, so its L2 serves neighbouring row segments (a
+// gain for the 4 KiB stride of a 512 y pass, a loss for the z pass).
+__device__ __forceinline__ long long xcd_tile(long long b, long long n) {
+    constexpr long long kXcds = 8;
+    const long long per = n / kXcds, rem = n % kXcds, x = b % kXcds, i = b / kXcds;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
 template <class Cfg, class St, int KIND, bool INV>
 __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
     using R = typename St::R;
@@ -844,6 +856,9 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_static(const PassArgs a) {
     long long tile = blockIdx.x;
     if (tile >= a.total) return;
     const long long G = gridDim.x;
+    if constexpr (Cfg::kXO) {
+        if (G == a.total) tile = xcd_tile(tile, a.total);
+    }
     const long long es = KIND == kContiguous ? 1 : a.es;
     // tile -> (tx, w), advanced incrementally by G tiles per iteration
     long long tx, w, gx = G, gw = 0;
@@ -949,15 +964,6 @@ struct LanesCfg {
     static_assert(L == 32 || L == 64, "a tile is one or two lines per wavefront lane group");
 };
 
-// With one block per tile, workgroup b runs on XCD b mod 8 (the dispatcher
-// deals workgroups to the 8 XCDs in turn); this order gives each XCD one
-// contiguous run of tiles, so its L2 serves neighbouring row segments (a
-// gain for the 4 KiB stride of a 512 y pass, a loss for the z pass).
-__device__ __forceinline__ long long xcd_tile(long long b, long long n) {
-    constexpr long long kXcds = 8;
-    const long long per = n / kXcds, rem = n % kXcds, x = b % kXcds, i = b / kXcds;
-    return x * per + (x < rem ? x : rem) + i;
-}
 
 // NTM: the non-temporal hint on the loads (bit 0) and on the stores (bit 1).
 // REV: with one block per tile, the tiles in reverse order (the pass starts
@@ -1677,9 +1683,9 @@ inline Entry with_plain(Entry e, int plain) {
 }
 
 template <int N, int KIND, class St, int SB, int DT, int EPT = 0, int LREQ = 0, int PAD = 0, int PF = 1,
-          int NT = 0>
+          int NT = 0, int XO = 0>
 Entry make_entry(int cand) {
-    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>), EPT, LREQ, PAD, PF, NT>;
+    using Cfg = SCfg<N, KIND, SB, (int)sizeof(cx<typename St::R>), EPT, LREQ, PAD, PF, NT, XO>;
     static_assert(Cfg::kBlock <= 1024, "block too large");
     static_assert(Cfg::kLds <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
     static_assert(Cfg::S >= 1, "length must have a radix plan");

@@ -14,7 +14,8 @@ namespace dev {
 // strided: 1 no prefetch, 2 wide tile (EW elements per thread, LW lines), 3 wide tile with prefetch,
 // 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
 // 5 wide tile with non-temporal loads and stores; contiguous 3: non-temporal;
-// fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
+// fused multiply pass: 0 default shape, 1 wide tile (EW, LW); strided 512: 6, 7, 8 are 1, 2, 4
+// with each XCD taking a contiguous run of tiles
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 0, 0>(2),             \
@@ -32,6 +33,9 @@ std::vector<Entry> entries_c128() {
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384),
         CAND(128, 8, 16, 16, 16), CAND(256, 8, 16, 16, 16), CAND(512, 8, 16, 16, 16), CAND(1024, 16, 8, 32, 8),
+        make_entry<512, kStrided, StC128, 16, kC128, 0, 0, 0, 0, 0, 1>(6),
+        make_entry<512, kStrided, StC128, 16, kC128, 8, 16, 0, 0, 0, 1>(7),
+        make_entry<512, kStrided, StC128, 16, kC128, 16, 16, 0, 0, 0, 1>(8),
     };
 }
 

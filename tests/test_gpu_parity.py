@@ -239,7 +239,7 @@ def test_execute_argument_errors_on_device():
 
 
 @pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
-@pytest.mark.parametrize("dtype", [C64, F16], ids=["c64", "f16"])
+@pytest.mark.parametrize("dtype", [C64, C128, F16], ids=["c64", "c128", "f16"])
 @pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20), (4, 512, 80)], ids=str)
 def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, tmp_path, monkeypatch):
     """Every autotuner candidate (and persistent-grid size) runs the same
@@ -250,8 +250,10 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, 
     monkeypatch.setenv("CROFT_WISDOM", str(wisdom))
     nz, ny, nx = shape
     rng = np.random.Generator(np.random.PCG64(21))
-    if dtype == C64:
-        x = torch.from_numpy((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)).cuda()
+    full = dtype in (C64, C128)
+    if full:
+        npdt = np.complex64 if dtype == C64 else np.complex128
+        x = torch.from_numpy((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(npdt)).cuda()
         ein = None
     else:
         x = torch.from_numpy(rng.standard_normal(shape + (2,)).astype(np.float16)).cuda()
@@ -262,7 +264,7 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, 
         eout = torch.full((ny, nx), 99, dtype=torch.int8, device="cuda")
         plan = croft.croft_plan_create(nx, ny, nz, dtype, direction)
         info = croft.croft_plan_info(plan)
-        if dtype == C64:
+        if full:
             croft.croft_execute(plan, x, out)
         else:
             croft.croft_execute_scaled(plan, x, ein, out, eout)
@@ -281,8 +283,8 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, 
                 wisdom.write_text(f"{n} {kind} {dtype} {cand} {waves}\n")
                 got, got_e, ginfo = run()
                 chosen = [p for p in ginfo["passes"] if (p["n"], p["kind"]) == (n, kind)]
-                assert torch.equal(got.view(torch.int32) if dtype == C64 else got.view(torch.int16),
-                                   ref.view(torch.int32) if dtype == C64 else ref.view(torch.int16)), \
+                bits = {C64: torch.int32, C128: torch.int64}.get(dtype, torch.int16)
+                assert torch.equal(got.view(bits), ref.view(bits)), \
                     (n, kind, cand, waves)
                 assert torch.equal(got_e, ref_e)
                 tried += 1
