@@ -23,7 +23,8 @@ namespace dev {
 // XCD-contiguous order, 10 to 12 are 6 with that copy (non-temporal stores in 11, loads and stores
 // in 12); contiguous 3:
 // non-temporal;
-// fused multiply pass: 0 default shape, 1 wide tile (EW, LW)
+// fused multiply pass: 0 default shape, 1 wide tile (EW, LW); strided 384: 6 and 7 are 1 and 0
+// (without and with prefetch) in the XCD-contiguous tile order
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 0, 0>(2),             \
@@ -55,6 +56,9 @@ std::vector<Entry> entries_c64() {
         with_plain(make_lanes_entry<1024, StC64, kC64, 3, 512, false, false, true>(12), 6),
         with_plain(make_lanes_entry<512, StC64, kC64, 0, 256, false, false, true>(17), 8),
         with_plain(make_lanes_entry<512, StC64, kC64, 3, 256, false, false, true>(18), 8),
+        CAND(384, 16, 32, 32, 32),
+        make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 0, 0, 1>(6),
+        make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 1, 0, 1>(7),
     };
 }
 

@@ -240,7 +240,7 @@ def test_execute_argument_errors_on_device():
 
 @pytest.mark.parametrize("direction", [FWD, BWD], ids=["fwd", "bwd"])
 @pytest.mark.parametrize("dtype", [C64, C128, F16], ids=["c64", "c128", "f16"])
-@pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20), (4, 512, 80)], ids=str)
+@pytest.mark.parametrize("shape", [(6, 256, 512), (3, 1024, 20), (4, 512, 80), (2, 384, 96)], ids=str)
 def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, tmp_path, monkeypatch):
     """Every autotuner candidate (and persistent-grid size) runs the same
     arithmetic in the same order, so the outputs agree bit for bit, in both
