@@ -1349,12 +1349,33 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
             }
         } else {
             const cx<R> *X = reinterpret_cast<const cx<R> *>(a.in) + q0 * H;
+            // the tile's spectra into LDS, every load of a thread in flight
+            // before its first LDS store where that takes at most 16 values
+            constexpr int kIter = (L * H + Cfg::kBlock - 1) / Cfg::kBlock;
+            if constexpr (kIter <= 16) {
+                cx<R> v[kIter];
+#pragma unroll
+                for (int it = 0; it < kIter; ++it) {
+                    const int i = tid + it * Cfg::kBlock;
+                    if (i < nl * H) v[it] = X[i];
+                }
+#pragma unroll
+                for (int it = 0; it < kIter; ++it) {
+                    const int i = tid + it * Cfg::kBlock;
+                    if (i < nl * H) {
+                        const int ln = i / H, k = i - ln * H;
+                        if (k < M) at(ln, k) = v[it];
+                        else nyq[ln] = v[it];
+                    }
+                }
+            } else {
 #pragma unroll 1
-            for (int i = tid; i < nl * H; i += Cfg::kBlock) {
-                const int ln = i / H, k = i - ln * H;
-                const cx<R> v = X[i];
-                if (k < M) at(ln, k) = v;
-                else nyq[ln] = v;
+                for (int i = tid; i < nl * H; i += Cfg::kBlock) {
+                    const int ln = i / H, k = i - ln * H;
+                    const cx<R> v = X[i];
+                    if (k < M) at(ln, k) = v;
+                    else nyq[ln] = v;
+                }
             }
             __syncthreads();
             // pairs (k, M - k), 0 <= k <= M/2, merged in place; k = 0 pairs with X[M]
