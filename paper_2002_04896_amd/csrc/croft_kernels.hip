@@ -48,15 +48,23 @@ __device__ __forceinline__ void generic_stage(const cx<R> *src, cx<R> *dst, cons
     }
 }
 
-template <class St, int KIND>
+// TWL: the length-n twiddle table is copied into LDS ahead of the line
+// buffers (one global read per block instead of one per twiddled butterfly
+// and stage), where the planner found room for it.
+template <class St, int KIND, bool TWL>
 __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
     using R = typename St::R;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = a.n, T = a.T, L = a.L;
-    cx<R> *buf0 = reinterpret_cast<cx<R> *>(smem);
+    cx<R> *buf0 = reinterpret_cast<cx<R> *>(smem) + (TWL ? n : 0);
     cx<R> *buf1 = buf0 + (size_t)L * n;
     unsigned *red = reinterpret_cast<unsigned *>(buf1 + (size_t)L * n);
     const cx<R> *tw = reinterpret_cast<const cx<R> *>(a.tw);
+    if constexpr (TWL) {
+        cx<R> *twl = reinterpret_cast<cx<R> *>(smem);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) twl[i] = tw[i];
+        tw = twl;  // made visible by the barrier after the line loads
+    }
     const int tid = threadIdx.x;
     const int l = KIND == kContiguous ? tid / T : tid % L;
     const int t = KIND == kContiguous ? tid % T : tid / L;
@@ -66,8 +74,11 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
         q = (long long)blockIdx.x * L + l;
         w = 0;
     } else {
-        q = ((long long)blockIdx.x % a.ntiles) * L + l;
-        w = (long long)blockIdx.x / a.ntiles;
+        // each XCD takes a contiguous run of tiles: the narrow rows of
+        // neighbouring tiles share 128-byte lines, which then meet in one L2
+        const long long b = xcd_tile(blockIdx.x, gridDim.x);
+        q = (b % a.ntiles) * L + l;
+        w = b / a.ntiles;
     }
     const bool valid = active && q < (KIND == kContiguous ? a.nlines : a.es);
     const long long es = KIND == kContiguous ? 1 : a.es;
@@ -79,17 +90,28 @@ __global__ void __launch_bounds__(256) fft_generic(const PassArgs a) {
         ebase = (int)exp_line_index(m, q, w, m.a0, m.a1, m.a2);
         if (active && t == 0) red[l] = 0u;
     }
-    // load the line into buf0 (consecutive t read consecutive e)
+    // load the line into buf0 (consecutive t read consecutive e), up to 8
+    // loads of a thread in flight before their LDS stores
     if (active) {
-        for (int e = t; e < n; e += T) {
-            cx<R> v = {R(0), R(0)};
-            if (valid) {
-                int ex = 0;
-                if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + a.em.a3 * e] : 0;
-                v = St::decode(St::fetch(a.in, base + es * e), ex);
-                if (inv) v = {v.y, v.x};
+        constexpr int kChunk = 8;
+        for (int e0 = t; e0 < n; e0 += kChunk * T) {
+            cx<R> v[kChunk];
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                const int e = e0 + c * T;
+                v[c] = {R(0), R(0)};
+                if (valid && e < n) {
+                    int ex = 0;
+                    if constexpr (St::kHalf) ex = a.in_exp ? (int)a.in_exp[ebase + a.em.a3 * e] : 0;
+                    v[c] = St::decode(St::fetch(a.in, base + es * e), ex);
+                    if (inv) v[c] = {v[c].y, v[c].x};
+                }
             }
-            buf0[glds<KIND>(l, e, n, L)] = v;
+#pragma unroll
+            for (int c = 0; c < kChunk; ++c) {
+                const int e = e0 + c * T;
+                if (e < n) buf0[glds<KIND>(l, e, n, L)] = v[c];
+            }
         }
     }
     __syncthreads();
@@ -241,21 +263,26 @@ const std::vector<Entry> &table() {
     return t;
 }
 
-const void *generic_func(int kind, int dtype) {
+template <bool TWL>
+const void *generic_func_t(int kind, int dtype) {
     if (kind == kContiguous) {
         switch (dtype) {
-            case kC64: return reinterpret_cast<const void *>(&fft_generic<StC64, kContiguous>);
-            case kC128: return reinterpret_cast<const void *>(&fft_generic<StC128, kContiguous>);
-            case kC16F: return reinterpret_cast<const void *>(&fft_generic<StHalf<false>, kContiguous>);
-            default: return reinterpret_cast<const void *>(&fft_generic<StHalf<true>, kContiguous>);
+            case kC64: return reinterpret_cast<const void *>(&fft_generic<StC64, kContiguous, TWL>);
+            case kC128: return reinterpret_cast<const void *>(&fft_generic<StC128, kContiguous, TWL>);
+            case kC16F: return reinterpret_cast<const void *>(&fft_generic<StHalf<false>, kContiguous, TWL>);
+            default: return reinterpret_cast<const void *>(&fft_generic<StHalf<true>, kContiguous, TWL>);
         }
     }
     switch (dtype) {
-        case kC64: return reinterpret_cast<const void *>(&fft_generic<StC64, kStrided>);
-        case kC128: return reinterpret_cast<const void *>(&fft_generic<StC128, kStrided>);
-        case kC16F: return reinterpret_cast<const void *>(&fft_generic<StHalf<false>, kStrided>);
-        default: return reinterpret_cast<const void *>(&fft_generic<StHalf<true>, kStrided>);
+        case kC64: return reinterpret_cast<const void *>(&fft_generic<StC64, kStrided, TWL>);
+        case kC128: return reinterpret_cast<const void *>(&fft_generic<StC128, kStrided, TWL>);
+        case kC16F: return reinterpret_cast<const void *>(&fft_generic<StHalf<false>, kStrided, TWL>);
+        default: return reinterpret_cast<const void *>(&fft_generic<StHalf<true>, kStrided, TWL>);
     }
+}
+
+const void *generic_func(int kind, int dtype, bool twl) {
+    return twl ? generic_func_t<true>(kind, dtype) : generic_func_t<false>(kind, dtype);
 }
 
 // One block of 256 threads: thread i sums partial[i], partial[i + 256], ...
@@ -341,6 +368,8 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
     const size_t per_line = 2 * (size_t)n * cb + 4;
     int lds_lines = (int)((160 * 1024) / per_line);
     if (lds_lines < 1) return false;
+    // the twiddle table in LDS where it leaves room for the lines below
+    const size_t table = (size_t)n * cb;
     int L;
     if (kind == kContiguous) {
         L = 256 / T;
@@ -354,7 +383,10 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
     int p2 = 1;  // round down to a power of two
     while (p2 * 2 <= L) p2 *= 2;
     L = p2;
-    cfg->func = cfg->func_inv = generic_func(kind, dtype);
+    // Twiddles are read from the second stage on; a plan of at most one
+    // stage reads none, and a length-1 pass has no table at all.
+    const bool twl = p.S >= 2 && table + (size_t)L * per_line <= 160 * 1024;
+    cfg->func = cfg->func_inv = generic_func(kind, dtype, twl);
     cfg->generic = true;
     cfg->bluestein = 0;
     cfg->candidate = 0;
@@ -363,7 +395,7 @@ bool select_kernel(int n, int kind, int dtype, bool force_generic, int cand, Ker
     cfg->threads_per_line = T;
     cfg->lines = L;
     cfg->block = ((T * L + 63) / 64) * 64;
-    cfg->lds = (size_t)L * per_line;
+    cfg->lds = (twl ? table : 0) + (size_t)L * per_line;
     cfg->nstages = p.S;
     for (int s = 0; s < p.S; ++s) cfg->radix[s] = p.r[s];
     return true;
@@ -428,7 +460,9 @@ bool select_generic_conv(int n, int dtype, KernelConfig *cfg) {
     if (!select_kernel(n, kStrided, dtype, true, 0, cfg) || cfg->bluestein) return false;
     cfg->func = cfg->func_inv = dtype == kC64 ? reinterpret_cast<const void *>(&fft_generic_conv<StC64>)
                                               : reinterpret_cast<const void *>(&fft_generic_conv<StC128>);
-    cfg->lds = std::max(cfg->lds, (size_t)cfg->block * sizeof(double));  // the block sum reuses the line buffers
+    // two line buffers, no twiddle table; the block sum reuses the line buffers
+    const size_t lines = (size_t)cfg->lines * 2 * n * (dtype == kC128 ? 16 : 8);
+    cfg->lds = std::max(lines, (size_t)cfg->block * sizeof(double));
     return true;
 }
 

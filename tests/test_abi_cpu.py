@@ -173,6 +173,30 @@ def test_describe_generic_fallback_and_skipped_axes():
     assert passes[0]["axis"] == "y" and passes[0]["kind"] == "contiguous"
 
 
+@pytest.mark.parametrize("args", [(1, 1, 1), (1, 1, 1, croft.CROFT_C16F), (1, 16, 1, croft.CROFT_C16B),
+                                  (480, 2, 3), (2, 480, 3, croft.CROFT_C128), (45, 1, 27), (2, 3, 2000),
+                                  (4000, 2, 1, croft.CROFT_C128), (6, 2, 5)])
+def test_runtime_radix_twiddles_in_lds_only_where_stages_read_them(args):
+    """The runtime-radix kernel copies the length-n twiddle table into LDS
+    only for plans of two or more stages (the first stage reads no twiddle,
+    and a length-1 pass has no table to copy), and only where it fits beside
+    the line buffers; its LDS is two line buffers plus one line maximum each."""
+    dt = args[3] if len(args) > 3 else croft.CROFT_C64
+    cb = 16 if dt == croft.CROFT_C128 else 8
+    _, passes = parse_describe(croft.croft_plan_describe(*args))
+    seen = 0
+    for p in passes:
+        if p["kernel"] != "generic" or p["bluestein"] != "0":
+            continue
+        seen += 1
+        n, L = int(p["n"]), int(p["L"])
+        lines = L * (2 * n * cb + 4)
+        stages = 0 if p["radices"] == "copy" else len(p["radices"].split("x"))
+        table = n * cb if stages >= 2 and n * cb + lines <= 160 * 1024 else 0
+        assert int(p["lds"]) == table + lines, (args, p)
+    assert seen
+
+
 def test_describe_half_runs_every_axis():
     _, passes = parse_describe(croft.croft_plan_describe(1, 16, 1, croft.CROFT_C16F))
     assert [p["axis"] for p in passes] == ["x", "y", "z"]
