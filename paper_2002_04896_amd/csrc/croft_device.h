@@ -1063,12 +1063,15 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
             const unsigned el = exp_line_index(m, cq, cw, m.a0, m.a1, m.a2) + (unsigned)m.a3 * (unsigned)h;
             gchar *const eb = uniform_gptr(a.in_exp, 0);
             const long long ea3t = m.a3 + tzz;
+            // every byte load in flight before the first is packed
+            unsigned bt[RP ? 64 : 1];
 #pragma unroll
-            for (int mm = 0; mm < (RP ? 64 : 0); ++mm) {
-                const unsigned b = *(const __attribute__((address_space(1))) uint8_t *)(
+            for (int mm = 0; mm < (RP ? 64 : 0); ++mm)
+                bt[mm] = *(const __attribute__((address_space(1))) uint8_t *)(
                     eb + ea3t * (t0 + tzz + (long long)TPL * mm) + lane_reg(el));
-                epk[mm >> 2] |= b << (8 * (mm & 3));
-            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mm = 0; mm < (RP ? 64 : 0); ++mm) epk[mm >> 2] |= bt[mm] << (8 * (mm & 3));
         }
     };
     bool ehoist = true;  // RP: every tile of the block reads the same exponents
@@ -1182,17 +1185,21 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
             __syncthreads();  // the previous readers of the area are done
+            // RP: the exchange addresses are made here, each tile, rather
+            // than hoisted out of the tile loop, where with the prefetched
+            // registers they would spill
+            const int tzx = RP ? opaque_zero() : 0;
 #pragma unroll
             for (int r = 0; r < 8; ++r)
 #pragma unroll
                 for (int p = 0; p < 8; ++p)
-                    xl[(64 * t + r + 8 * p) * L + l] = part ? v[8 * r + p].y : v[8 * r + p].x;
+                    xl[(64 * t + r + 8 * p) * L + l + tzx] = part ? v[8 * r + p].y : v[8 * r + p].x;
             __syncthreads();
 #pragma unroll
             for (int u = 0; u < NB2; ++u)
 #pragma unroll
                 for (int p = 0; p < TPL; ++p) {
-                    const R e = xl[(NB2 * t + u + 64 * p) * L + l];
+                    const R e = xl[(NB2 * t + u + 64 * p) * L + l + tzx];
                     if (part) y[TPL * u + p].y = e;
                     else y[TPL * u + p].x = e;
                 }
@@ -1225,12 +1232,14 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
         }
         int ex = 0;
         if constexpr (St::kHalf) {
-            // the line's maximum over its TPL threads
-            red[t * L + l] = __float_as_uint(mx);
+            // the line's maximum over its TPL threads (RP: addresses made
+            // each tile, as for the exchange)
+            const int tzr = RP ? opaque_zero() : 0;
+            red[t * L + l + tzr] = __float_as_uint(mx);
             __syncthreads();
-            unsigned mb = red[l];
+            unsigned mb = red[l + tzr];
 #pragma unroll
-            for (int k = 1; k < TPL; ++k) mb = max(mb, red[k * L + l]);
+            for (int k = 1; k < TPL; ++k) mb = max(mb, red[k * L + l + tzr]);
             ex = line_exponent(__uint_as_float(mb));
         }
         if (valid) {
