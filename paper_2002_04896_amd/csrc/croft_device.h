@@ -977,10 +977,16 @@ struct LanesCfg {
 // complete before them (vector memory counts in order), so waiting for
 // them leaves the stores in flight: 64 stores per lane follow them, and a
 // wait for at most 62 outstanding operations covers the copy.
-// RP (16-bit storage): the block issues its next tile's loads into
-// registers as soon as the current tile is decoded (64 registers of 16-bit
-// pairs), so they are in flight during the butterflies, the exchange and
-// the stores.  The input exponents sit packed four to a register; they are
+// RP (16-bit storage): the block loads its next tile into registers (64
+// registers of 16-bit pairs) during the current one: the first half as soon
+// as the current tile is decoded, the second after the exchange (a wave
+// holds at most 63 vector memory operations, and after the decode the
+// previous tile's stores still hold many of them), so they are in flight
+// during the butterflies, the exchange and the stores.  No address the
+// tile loop could hoist stays live across it (the exchange and line-maximum
+// addresses are made each tile): with the prefetched registers it would
+// spill, and each reload would wait for every load in flight.  The input
+// exponents sit packed four to a register; they are
 // loaded once per block where every tile of the block reads the same ones
 // (whole tiles, the exponent index independent of the plane, and the
 // block's line stride a multiple of the index period: the 512^3 z pass),
@@ -1045,13 +1051,15 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
     // RP: the raw values of the next tile, and the packed input exponents
     Raw rawn[RP ? 64 : 1];
     unsigned epk[RP ? 16 : 1];
-    auto issue_loads = [&](long long ctx, long long cw, int tzz) {
+    // positions t + TPL m, m0 <= m < m1, of tile (ctx, cw)
+    auto issue_loads = [&](long long ctx, long long cw, int tzz, int m0, int m1) {
         if (ctx * L + l < es) {
             gchar *const nb = uniform_gptr(a.in, (ctx * L + cw * es * N) * (long long)kS);
             const long long est = es + tzz;
 #pragma unroll
             for (int m = 0; m < 64; ++m)
-                rawn[m] = fetch_at<St, (NTM & 1) != 0>(nb, (t0 + tzz + (long long)TPL * m) * est, lane_b);
+                if (m >= m0 && m < m1)
+                    rawn[m] = fetch_at<St, (NTM & 1) != 0>(nb, (t0 + tzz + (long long)TPL * m) * est, lane_b);
         }
     };
     auto load_exponents = [&](long long ctx, long long cw, int tzz) {
@@ -1080,7 +1088,7 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
         const bool qinv = m.a0 == 0 || ((gx * L) % m.qmod == 0 && (a.ntiles * L) % m.qmod == 0);
         ehoist = G >= a.total || !a.in_exp ||
                  (es % L == 0 && m.a1 == 0 && qinv && (m.a2 == 0 || a.total == a.ntiles));
-        issue_loads(tx, w, opaque_zero());
+        issue_loads(tx, w, opaque_zero(), 0, 64);
         load_exponents(tx, w, opaque_zero());
     }
     bool first = true;
@@ -1116,7 +1124,10 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
 #pragma unroll
                 for (int m = 0; m < 64; ++m) v[m] = {R(0), R(0)};
             }
-            if (nt < a.total) issue_loads(ntx, nw, tz);
+            // the next tile's first half now, its second half after the
+            // exchange: a wave holds at most 63 vector memory operations,
+            // and the previous tile's stores are still in flight here
+            if (nt < a.total) issue_loads(ntx, nw, tz, 0, 32);
             __builtin_amdgcn_sched_barrier(0);
         } else if (valid) {
             unsigned elane = 0;
@@ -1203,6 +1214,13 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
                     if (part) y[TPL * u + p].y = e;
                     else y[TPL * u + p].x = e;
                 }
+        }
+        if constexpr (RP) {
+            if (nt < a.total) {
+                __builtin_amdgcn_sched_barrier(0);
+                issue_loads(ntx, nw, opaque_zero(), 32, 64);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
         if constexpr (PF) {
             if (nt < a.total) {

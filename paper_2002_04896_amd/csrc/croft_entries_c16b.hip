@@ -19,7 +19,8 @@ namespace dev {
 // 12 in the XCD-contiguous order, 15 and 16 are 6 with the hint on the loads only and on
 // the stores only; 17 and 18 are 6 and 16 copying the first half of the next tile into LDS
 // during the current one (whole tiles, persistent grids); 19 and 20 are 16 and 6 loading
-// the next tile into registers during the current one (persistent grids);
+// the next tile into registers during the current one (persistent grids); 21 and 22
+// are 8 and 9 with the copy of 17 (256-thread blocks, two per CU);
 // at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order, 10 and 11 are 6 and 7 with that
 // copy; contiguous 3: non-temporal
 #define CAND(N, EW, LW, EW2, LW2)                                                \
@@ -48,6 +49,8 @@ std::vector<Entry> entries_c16b() {
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 2, 512, false, false, true>(18), 6),
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 2, 512, false, false, false, true>(19), 20),
         make_lanes_entry<512, StHalf<true>, kC16B, 0, 512, false, false, false, true>(20),
+        with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 0, 256, false, false, true>(21), 8),
+        with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 3, 256, false, false, true>(22), 8),
         make_lanes_entry<1024, StHalf<true>, kC16B, 0>(6), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3>(7), 6),
         make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3, 512, true>(9), 8),
         with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, false, false, true>(10), 6),

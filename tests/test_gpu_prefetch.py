@@ -1,6 +1,6 @@
 """The strided candidates that fetch their next tile while the current one
 finishes: into LDS (the first half, global_load_lds; persistent grids of
-whole tiles) or, for 16-bit storage, into registers (with the input
+whole tiles, in 512- or 256-thread blocks) or, for 16-bit storage, into registers (with the input
 exponents packed four to a register, loaded once per block where every
 tile of the block shares them).  They run the same butterflies as the other
 candidates of their length, so forcing one through the wisdom file must
@@ -26,8 +26,8 @@ CASES = [
     (C64, (512, 256, 128), 2, 512, (17, 18)),
     (C64, (256, 512, 128), 1, 512, (17, 18)),
     (C64, (1024, 64, 256), 2, 1024, (10, 11, 12)),
-    (F16, (512, 128, 256), 2, 512, (17, 18)),
-    (BF16, (512, 128, 256), 2, 512, (17, 18)),
+    (F16, (512, 128, 256), 2, 512, (17, 18, 21, 22)),
+    (BF16, (512, 128, 256), 2, 512, (17, 18, 21, 22)),
     (F16, (1024, 128, 128), 2, 1024, (10, 11)),
     # register prefetch: exponents once per block (z, nx = 256), once per
     # tile (z, nx = 100: the block's line stride is no multiple of nx; the
@@ -36,7 +36,7 @@ CASES = [
     (BF16, (512, 128, 256), 2, 512, (19, 20)),
     (F16, (512, 64, 100), 2, 512, (19, 20)),
     (BF16, (512, 21, 100), 2, 512, (19, 20)),
-    (F16, (128, 512, 256), 1, 512, (19, 20)),
+    (F16, (128, 512, 256), 1, 512, (19, 20, 21, 22)),
 ]
 
 
