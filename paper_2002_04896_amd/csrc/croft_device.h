@@ -580,21 +580,24 @@ __device__ __forceinline__ unsigned lane_reg(unsigned v) {
 }
 
 // base: the tile's origin, made uniform once per tile (uniform_gptr); the
-// uniform element offset is then added in scalar registers.
-template <class St, bool NT = false>
+// uniform element offset is then added in scalar registers.  REMAT: the lane
+// offset re-materialised here (the one-line-per-lane kernels, where the copy
+// is the load's own destination register); otherwise the caller passes one
+// copy made in the same block as a group of accesses, which all fold it.
+template <class St, bool NT = false, bool REMAT = true>
 __device__ __forceinline__ typename St::Raw fetch_at(gchar *base, long long uniform_elem, unsigned lane_bytes) {
     using Raw = typename St::Raw;
-    lane_bytes = lane_reg(lane_bytes);
+    if constexpr (REMAT) lane_bytes = lane_reg(lane_bytes);
     gchar *b = base + uniform_elem * (long long)sizeof(Raw);
     const __attribute__((address_space(1))) Raw *q = (const __attribute__((address_space(1))) Raw *)(b + lane_bytes);
     if constexpr (NT) return __builtin_nontemporal_load(q);
     return *q;
 }
 
-template <class St, bool NT = false>
+template <class St, bool NT = false, bool REMAT = true>
 __device__ __forceinline__ void store_at(gchar *base, long long uniform_elem, unsigned lane_bytes,
                                          cx<typename St::R> v, int ex) {
-    lane_bytes = lane_reg(lane_bytes);
+    if constexpr (REMAT) lane_bytes = lane_reg(lane_bytes);
     gchar *b = base + uniform_elem * (long long)sizeof(typename St::Raw);
     if constexpr (NT) {
         __builtin_nontemporal_store(St::pack(v, ex), (__attribute__((address_space(1))) typename St::Raw *)(b + lane_bytes));
@@ -636,10 +639,11 @@ __device__ __forceinline__ void fetch_tile(const PassArgs &a, const TileCoord &c
     for (int b = 0; b < TL::B0; ++b) {
         const int j = t + b * Cfg::T;
         if ((TL::NB0 % Cfg::T) == 0 || j < TL::NB0) {
+            const unsigned lr = lane_reg(lane);  // one copy for the group's loads
 #pragma unroll
             for (int q = 0; q < TL::R0; ++q) {
                 const long long u = ut + (long long)(b * Cfg::T + q * TL::NB0) * es;
-                const typename St::Raw r = fetch_at<St, Cfg::kNT>(ib, u, lane);
+                const typename St::Raw r = fetch_at<St, Cfg::kNT, false>(ib, u, lr);
                 int ex = 0;
                 if constexpr (St::kHalf && !kLineScaled<St, KIND>)
                     ex = *(const __attribute__((address_space(1))) int8_t *)(eb + ea3 * (b * Cfg::T + q * TL::NB0) +
@@ -779,10 +783,11 @@ __device__ __forceinline__ void static_stage(const PassArgs &a, cx<typename St::
             for (int b = 0; b < B; ++b) {
                 const int j = t + b * T;
                 if (!kGuard || j < NB) {
+                    const unsigned lr = lane_reg(lane);  // one copy for the group's stores
 #pragma unroll
                     for (int q = 0; q < RAD; ++q) {
                         const long long u = ut + (long long)(b * T + q * NB) * es;
-                        store_at<St, Cfg::kNT>(ob, u, lane, maybe_swap<INV>(v[b][q]), ex);
+                        store_at<St, Cfg::kNT, false>(ob, u, lr, maybe_swap<INV>(v[b][q]), ex);
                     }
                 }
             }
@@ -1199,7 +1204,7 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
             // RP: the exchange addresses are made here, each tile, rather
             // than hoisted out of the tile loop, where with the prefetched
             // registers they would spill
-            const int tzx = RP ? opaque_zero() : 0;
+            const int tzx = (RP || N == 1024) ? opaque_zero() : 0;
 #pragma unroll
             for (int r = 0; r < 8; ++r)
 #pragma unroll
@@ -1263,13 +1268,18 @@ __global__ void __launch_bounds__(BLOCK) fft_lanes(const PassArgs a) {
         if (valid) {
             gchar *const ob = uniform_gptr(a.out, tbase * (long long)sizeof(typename St::Raw));
             const long long est = es + tz;
+            // one copy of the lane offset for the tile's stores, where the
+            // kernel has a register to spare for it (not at 256 VGPRs: the
+            // register prefetch and length 1024 copy it at each store)
+            constexpr bool kShare = N == 512 && !RP;
+            const unsigned ls = kShare ? lane_reg(lane_s) : lane_s;
 #pragma unroll
             for (int u = 0; u < NB2; ++u)
 #pragma unroll
                 for (int p = 0; p < TPL; ++p) {
                     // position NB2 t + u + 64 p: NB2 t0 + u + 64 p uniform, NB2 h in lane_s
                     const long long pos = (long long)NB2 * (t0 + tz) + u + 64 * p;
-                    store_at<St, (NTM & 2) != 0>(ob, pos * est, lane_s, maybe_swap<INV>(y[TPL * u + p]), ex);
+                    store_at<St, (NTM & 2) != 0, !kShare>(ob, pos * est, ls, maybe_swap<INV>(y[TPL * u + p]), ex);
                 }
             if constexpr (St::kHalf) {
                 if (t == 0 && a.out_exp) {
