@@ -105,10 +105,13 @@ const BuiltinAxis kBuiltinAxis[] = {
     {1024, 1, 3, 1, 6, 1},
     {1024, 1, 3, 2, 9, 0},
     {512, 1, 0, 1, 15, 0},
-    // complex64 z at 512: the same 256-thread blocks, non-temporal, copying
-    // the first half of the next tile into LDS during the current one, two
-    // waves of resident blocks (0.400 -> 0.382 ms, both directions)
-    {512, 1, 0, 2, 18, 2},
+    // complex64 z at 512: the same 256-thread blocks, non-temporal, the
+    // candidate that copies half a tile into LDS, one block per tile (so each
+    // block copies the first half of its own tile): 0.400 -> 0.382 ms on two
+    // waves of resident blocks, then 0.382 -> 0.371 ms with one block per
+    // tile (both directions, two GPUs; real plans 0.618 -> 0.615 ms forward,
+    // 0.684 -> 0.677 ms backward)
+    {512, 1, 0, 2, 18, 0},
     {512, 1, 2, 1, 14, 0},
     {512, 1, 3, 1, 14, 0},
     // complex128 y at 512: the 16-line tile in the XCD-contiguous order, one

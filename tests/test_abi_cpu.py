@@ -225,14 +225,14 @@ def test_builtin_wisdom_picks_one_line_per_lane_at_512(tmp_path, monkeypatch):
     # lane (8 threads per line) in 32-line tiles (256-byte rows, 256-thread
     # blocks) on both axes, the y pass one block per tile with non-temporal
     # loads and the tiles in reverse order, the z pass with non-temporal
-    # loads and stores, two waves of resident blocks, copying the next
-    # tile's first half into LDS
+    # loads and stores, one block per tile, the tile's first half copied
+    # into LDS
     for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
         passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C64, direction)
         assert [p["candidate"] for p in passes][1:] == ["15", "18"]
         for p in passes[1:]:
             assert (p["T"], p["L"], p["block"]) == ("8", "32", "256")
-        assert [p["waves"] for p in passes][1:] == ["0", "2"]
+        assert [p["waves"] for p in passes][1:] == ["0", "0"]
     # a wisdom line for any axis comes before the built-in per-axis choices
     passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 2 1\n", 512, 512, 512)
     assert [p["candidate"] for p in passes][1:] == ["2", "2"]

@@ -75,7 +75,7 @@ def test_next_tile_fetch_candidates_give_identical_bits(case, tmp_path, monkeypa
         wisdom.write_text(f"{n} 1 {dtype} 6 1 {axis}\n")      # a candidate without the copy
         ref, ref_e, _ = run(dtype, shape, direction, d_in, e_in)
         for cand in cands:
-            for waves in (1, 2):
+            for waves in (0, 1, 2):  # 0: one block per tile (a block copies its own tile's first half)
                 print(f"dtype {dtype} shape {shape} axis {axis} cand {cand} waves {waves} dir {direction}",
                       flush=True)
                 wisdom.write_text(f"{n} 1 {dtype} {cand} {waves} {axis}\n")
