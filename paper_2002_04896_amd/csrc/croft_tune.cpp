@@ -114,9 +114,12 @@ const BuiltinAxis kBuiltinAxis[] = {
     {512, 1, 0, 2, 18, 0},
     {512, 1, 2, 1, 14, 0},
     {512, 1, 3, 1, 14, 0},
-    // complex128 y at 512: the 16-line tile in the XCD-contiguous order, one
-    // block per tile (0.812-0.821 -> 0.794-0.799 ms, both directions)
-    {512, 1, 1, 1, 6, 0},
+    // complex128 y at 512: the wide tile with fewer threads, one block per
+    // tile.  The 16-line tile in the XCD-contiguous order (candidate 6) runs
+    // the y pass itself faster (0.79-0.80 against 0.80-0.81 ms), but the z
+    // pass after it takes 0.91 against 0.86 ms: the transform is faster with
+    // this one (2.404-2.423 against 2.440-2.461 ms, both directions)
+    {512, 1, 1, 1, 4, 0},
     // 16-bit storage z at 512: 64-line tiles loading the next tile into
     // registers during the current one (BF16 0.272-0.277 -> 0.264-0.268 ms,
     // FP16 the same within the spread, both directions, two GPUs)
