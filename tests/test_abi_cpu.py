@@ -296,6 +296,19 @@ def test_builtin_half_storage_one_line_per_lane_at_512(tmp_path, monkeypatch):
         assert (passes[2]["T"], passes[2]["L"], passes[2]["block"]) == ("8", "64", "512")
 
 
+def test_builtin_complex128_choices_at_512(tmp_path, monkeypatch):
+    # complex128 at 512, both directions: x the non-temporal contiguous tile,
+    # y and z the wide tile with fewer threads (16-line tiles, 512-thread
+    # blocks), y one block per tile, z on two waves of resident blocks (the
+    # XCD-ordered y tile is the faster y pass alone but slows the z pass)
+    for direction in (croft.CROFT_FORWARD, croft.CROFT_BACKWARD):
+        passes = _describe_with_wisdom(tmp_path, monkeypatch, "", 512, 512, 512, croft.CROFT_C128, direction)
+        assert [p["candidate"] for p in passes] == ["3", "4", "4"]
+        assert [p["waves"] for p in passes] == ["0", "0", "2"]
+        for p in passes[1:]:
+            assert (p["L"], p["block"]) == ("16", "512")
+
+
 def test_builtin_one_line_per_lane_at_1024(tmp_path, monkeypatch):
     # complex64 strided passes of length 1024: 16 threads per line, 32-line
     # tiles (256-byte rows) in 512-thread blocks, one block per tile, both
