@@ -156,7 +156,9 @@ def test_describe_512_cube():
 
 @pytest.mark.parametrize("n,rad", [(384, "3x8x16"), (48, "3x16"), (60, "5x3x4"), (72, "3x3x8"),
                                    (80, "5x16"), (96, "3x8x4"), (100, "5x5x4"), (128, "8x16"),
-                                   (1024, "8x8x16"), (32, "8x4"), (2, "2"), (4096, "8x8x8x8")])
+                                   (1024, "8x8x16"), (32, "8x4"), (2, "2"), (4096, "8x8x8x8"),
+                                   (120, "5x3x8"), (160, "5x8x4"), (192, "3x8x8"), (240, "5x3x16"),
+                                   (320, "5x8x8"), (480, "5x3x8x4")])
 def test_describe_factorisations(n, rad):
     _, passes = parse_describe(croft.croft_plan_describe(n, 2, 3))
     assert passes[0]["radices"] == rad and passes[0]["kernel"] == "static"
