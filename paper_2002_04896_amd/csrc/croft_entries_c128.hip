@@ -32,7 +32,8 @@ std::vector<Entry> entries_c128() {
         DEF(2),   DEF(4),   DEF(8),   DEF(16),   DEF(32),   DEF(64),   DEF(128),
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384), DEF(120), DEF(160),
-        DEF(192), DEF(240), DEF(320), DEF(480),
+        DEF(192), DEF(240), DEF(320), DEF(480), DEF(200), DEF(288), DEF(360),
+        DEF(400), DEF(576), DEF(640), DEF(720), DEF(768), DEF(960),
         CAND(128, 8, 16, 16, 16), CAND(256, 8, 16, 16, 16), CAND(512, 8, 16, 16, 16), CAND(1024, 16, 8, 32, 8),
         make_entry<512, kStrided, StC128, 16, kC128, 0, 0, 0, 0, 0, 1>(6),
         make_entry<512, kStrided, StC128, 16, kC128, 8, 16, 0, 0, 0, 1>(7),

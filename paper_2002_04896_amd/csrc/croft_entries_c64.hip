@@ -41,7 +41,8 @@ std::vector<Entry> entries_c64() {
         DEF(2),   DEF(4),   DEF(8),   DEF(16),   DEF(32),   DEF(64),   DEF(128),
         DEF(256), DEF(512), DEF(1024), DEF(2048), DEF(4096), DEF(48),  DEF(60),
         DEF(72),  DEF(80),  DEF(96),  DEF(100), DEF(384), DEF(120), DEF(160),
-        DEF(192), DEF(240), DEF(320), DEF(480),
+        DEF(192), DEF(240), DEF(320), DEF(480), DEF(200), DEF(288), DEF(360),
+        DEF(400), DEF(576), DEF(640), DEF(720), DEF(768), DEF(960),
         CAND(128, 16, 32, 32, 32), CAND(256, 16, 32, 32, 32), CAND(512, 16, 32, 32, 32), CAND(1024, 32, 16, 64, 16),
         make_lanes_entry<512, StC64, kC64, 0>(6), with_plain(make_lanes_entry<512, StC64, kC64, 3>(7), 6),
         make_lanes_entry<512, StC64, kC64, 0, 256>(8), with_plain(make_lanes_entry<512, StC64, kC64, 3, 256>(9), 8),

@@ -158,10 +158,17 @@ def test_describe_512_cube():
                                    (80, "5x16"), (96, "3x8x4"), (100, "5x5x4"), (128, "8x16"),
                                    (1024, "8x8x16"), (32, "8x4"), (2, "2"), (4096, "8x8x8x8"),
                                    (120, "5x3x8"), (160, "5x8x4"), (192, "3x8x8"), (240, "5x3x16"),
-                                   (320, "5x8x8"), (480, "5x3x8x4")])
+                                   (320, "5x8x8"), (480, "5x3x8x4"), (200, None), (288, None), (360, None),
+                                   (400, None), (576, None), (640, None), (720, None), (768, None), (960, None)])
 def test_describe_factorisations(n, rad):
     _, passes = parse_describe(croft.croft_plan_describe(n, 2, 3))
-    assert passes[0]["radices"] == rad and passes[0]["kernel"] == "static"
+    assert passes[0]["kernel"] == "static"
+    if rad is not None:
+        assert passes[0]["radices"] == rad
+    prod = 1
+    for r in passes[0]["radices"].split("x"):
+        prod *= int(r)
+    assert prod == n
 
 
 def test_describe_generic_fallback_and_skipped_axes():

@@ -46,7 +46,9 @@ SHAPES = [(100, 60, 48), (48, 100, 60), (27, 45, 60), (3, 128, 5), (8, 30, 1), (
           (1, 1, 8), (64, 1, 1), (80, 72, 96), (5, 3, 2), (16, 384, 12), (2, 6, 1000),
           (12, 3, 1024), (9, 2048, 2), (2, 2, 4096), (4096, 3, 2), (25, 36, 40),
           (1024, 3, 40), (5, 1024, 33),   # strided 1024: 32-line tiles with a ragged tail
-          (4, 240, 120), (480, 2, 3), (3, 320, 192), (160, 5, 7)]   # compiled 2^a 3^b 5^c lengths
+          (4, 240, 120), (480, 2, 3), (3, 320, 192), (160, 5, 7),   # compiled 2^a 3^b 5^c lengths
+          (3, 200, 288), (360, 3, 4), (2, 400, 3), (3, 2, 576), (640, 2, 3), (3, 720, 2), (2, 3, 768),
+          (960, 2, 2)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=str)
