@@ -36,6 +36,15 @@ namespace dev {
         make_entry<N, kStrided, StC64, 8, kC64, EW, LW, 0, 0, 1>(5), \
         make_conv_entry<N, StC64, 8, kC64, EW, LW>(1)
 
+// the larger compiled 2^a 3^b 5^c lengths (16-line strided tiles): the
+// streaming contiguous tile, the strided tile without prefetch, and both
+// strided tiles in the XCD-contiguous order (numbered as at 384)
+#define XCAND(N)                                                                  \
+    make_entry<N, kContiguous, StC64, 8, kC64, 0, 0, 0, 1, 1>(3),                 \
+        make_entry<N, kStrided, StC64, 8, kC64, 0, 0, 0, 0>(1),                   \
+        make_entry<N, kStrided, StC64, 8, kC64, 0, 0, 0, 0, 0, 1>(6),             \
+        make_entry<N, kStrided, StC64, 8, kC64, 0, 0, 0, 1, 0, 1>(7)
+
 std::vector<Entry> entries_c64() {
     return {
         DEF(2),   DEF(4),   DEF(8),   DEF(16),   DEF(32),   DEF(64),   DEF(128),
@@ -61,6 +70,7 @@ std::vector<Entry> entries_c64() {
         CAND(384, 16, 32, 32, 32),
         make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 0, 0, 1>(6),
         make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 1, 0, 1>(7),
+        XCAND(400), XCAND(480), XCAND(576), XCAND(640), XCAND(720), XCAND(768), XCAND(960),
     };
 }
 
