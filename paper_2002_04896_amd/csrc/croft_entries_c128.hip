@@ -27,6 +27,15 @@ namespace dev {
         make_entry<N, kStrided, StC128, 16, kC128, EW, LW, 0, 0, 1>(5), \
         make_conv_entry<N, StC128, 16, kC128, EW, LW>(1)
 
+// the larger compiled 2^a 3^b 5^c lengths: the streaming contiguous tile, the
+// strided tile without prefetch, and both strided tiles in the XCD-contiguous
+// order (numbered as the complex64 ones)
+#define XCAND(N)                                                                   \
+    make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 0, 1, 1>(3),               \
+        make_entry<N, kStrided, StC128, 16, kC128, 0, 0, 0, 0>(1),                 \
+        make_entry<N, kStrided, StC128, 16, kC128, 0, 0, 0, 0, 0, 1>(6),           \
+        make_entry<N, kStrided, StC128, 16, kC128, 0, 0, 0, 1, 0, 1>(7)
+
 std::vector<Entry> entries_c128() {
     return {
         DEF(2),   DEF(4),   DEF(8),   DEF(16),   DEF(32),   DEF(64),   DEF(128),
@@ -38,6 +47,7 @@ std::vector<Entry> entries_c128() {
         make_entry<512, kStrided, StC128, 16, kC128, 0, 0, 0, 0, 0, 1>(6),
         make_entry<512, kStrided, StC128, 16, kC128, 8, 16, 0, 0, 0, 1>(7),
         make_entry<512, kStrided, StC128, 16, kC128, 16, 16, 0, 0, 0, 1>(8),
+        XCAND(400), XCAND(480), XCAND(576), XCAND(640), XCAND(720), XCAND(768), XCAND(960),
     };
 }
 
