@@ -33,6 +33,15 @@ namespace dev {
         make_entry<N, kContiguous, StHalf<true>, 4, kC16B, 0, 0, 0, 1, 1>(3), \
         make_entry<N, kStrided, StHalf<true>, 4, kC16B, EW, LW, 0, 0, 1>(5)
 
+// the larger compiled 2^a 3^b 5^c lengths: the streaming contiguous tile, the
+// strided tile without prefetch, and both strided tiles in the XCD-contiguous
+// order (numbered as the complex64 ones)
+#define XCAND(N)                                                                     \
+    make_entry<N, kContiguous, StHalf<true>, 4, kC16B, 0, 0, 0, 1, 1>(3),                 \
+        make_entry<N, kStrided, StHalf<true>, 4, kC16B, 0, 0, 0, 0>(1),                   \
+        make_entry<N, kStrided, StHalf<true>, 4, kC16B, 0, 0, 0, 0, 0, 1>(6),             \
+        make_entry<N, kStrided, StHalf<true>, 4, kC16B, 0, 0, 0, 1, 0, 1>(7)
+
 std::vector<Entry> entries_c16b() {
     return {
         DEF(2),   DEF(4),   DEF(8),   DEF(16),   DEF(32),   DEF(64),   DEF(128),
@@ -57,6 +66,7 @@ std::vector<Entry> entries_c16b() {
         make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3, 512, true>(9), 8),
         with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, false, false, true>(10), 6),
         with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3, 512, false, false, true>(11), 6),
+        XCAND(400), XCAND(480), XCAND(576), XCAND(640), XCAND(720), XCAND(768), XCAND(960),
     };
 }
 

@@ -154,9 +154,12 @@ def check_half_output(out_bits, out_exp, kind):
 
 @pytest.mark.parametrize("dtype", [F16, BF16], ids=["f16", "bf16"])
 # (512, 3, 40), (1024, 2, 36), (3, 1024, 40): one-line-per-lane strided passes
-# (z at 512 and 1024, y at 1024) with ragged last tiles
+# (z at 512 and 1024, y at 1024) with ragged last tiles; (3, 640, 5),
+# (768, 2, 3), (2, 720, 3): the XCD-ordered strided tiles of the larger
+# compiled lengths
 @pytest.mark.parametrize("shape", [(40, 48, 64), (27, 60, 45), (1, 16, 1), (6, 1, 100), (512, 3, 40),
-                                   (1024, 2, 36), (3, 1024, 40)], ids=str)
+                                   (1024, 2, 36), (3, 1024, 40), (3, 640, 5), (768, 2, 3), (2, 720, 3)],
+                         ids=str)
 def test_half_storage_against_oracle(dtype, shape):
     kind = HALF_KIND[dtype]
     v = synth.normal_c(shape, seed=7)
