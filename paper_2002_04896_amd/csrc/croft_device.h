@@ -1382,10 +1382,20 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
                 const cx<R> s = {(A.x + B.x) * R(0.5), (A.y + B.y) * R(0.5)};
                 const cx<R> d = {(A.x - B.x) * R(0.5), (A.y - B.y) * R(0.5)};
                 const cx<R> wd = cmul(w2(k), d);                         // w^k (A - B)/2
-                St::store(out, i, cx<R>{s.x + wd.y, s.y - wd.x}, 0);     // s - i wd
+                const cx<R> z = {s.x + wd.y, s.y - wd.x};                // s - i wd
+                if constexpr (Cfg::kNT)
+                    __builtin_nontemporal_store(St::pack(z, 0), reinterpret_cast<typename St::Raw *>(out) + i);
+                else
+                    St::store(out, i, z, 0);
             }
         } else {
             const cx<R> *X = reinterpret_cast<const cx<R> *>(a.in) + q0 * H;
+            auto load_x = [&](int i) -> cx<R> {
+                if constexpr (Cfg::kNT)
+                    return St::decode(__builtin_nontemporal_load(reinterpret_cast<const typename St::Raw *>(X) + i), 0);
+                else
+                    return X[i];
+            };
             // the tile's spectra into LDS, every load of a thread in flight
             // before its first LDS store where that takes at most 16 values
             constexpr int kIter = (L * H + Cfg::kBlock - 1) / Cfg::kBlock;
@@ -1394,7 +1404,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
 #pragma unroll
                 for (int it = 0; it < kIter; ++it) {
                     const int i = tid + it * Cfg::kBlock;
-                    if (i < nl * H) v[it] = X[i];
+                    if (i < nl * H) v[it] = load_x(i);
                 }
 #pragma unroll
                 for (int it = 0; it < kIter; ++it) {
@@ -1409,7 +1419,7 @@ __global__ void __launch_bounds__(Cfg::kBlock) fft_real_x(const PassArgs a) {
 #pragma unroll 1
                 for (int i = tid; i < nl * H; i += Cfg::kBlock) {
                     const int ln = i / H, k = i - ln * H;
-                    const cx<R> v = X[i];
+                    const cx<R> v = load_x(i);
                     if (k < M) at(ln, k) = v;
                     else nyq[ln] = v;
                 }
@@ -1785,16 +1795,17 @@ Entry make_lanes_entry(int cand) {
 }
 
 // The real x pass of length 2N on the contiguous configuration of length N.
-template <int N, class St, int SB, int DT>
+// NT: the non-temporal hint on the pass's global loads and stores (candidate 1)
+template <int N, class St, int SB, int DT, int NT = 0>
 Entry make_real_entry() {
-    using Cfg = SCfg<N, kContiguous, SB, (int)sizeof(cx<typename St::R>), 0, 0, 0, 1>;
+    using Cfg = SCfg<N, kContiguous, SB, (int)sizeof(cx<typename St::R>), 0, 0, 0, 1, NT>;
     using Lay = RealLds<Cfg, std::integral_constant<int, (int)sizeof(cx<typename St::R>)>>;
     static_assert(Lay::kBytes <= 160 * 1024, "LDS beyond the 160 KiB of a gfx950 workgroup");
     Entry e;
     e.n = N;
     e.kind = kRealX;
     e.dtype = DT;
-    e.cand = 0;
+    e.cand = NT;
     e.func[0] = reinterpret_cast<const void *>(&fft_real_x<Cfg, St, false>);
     e.func[1] = reinterpret_cast<const void *>(&fft_real_x<Cfg, St, true>);
     e.T = Cfg::T;

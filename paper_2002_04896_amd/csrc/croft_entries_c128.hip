@@ -48,6 +48,7 @@ std::vector<Entry> entries_c128() {
         make_entry<512, kStrided, StC128, 16, kC128, 8, 16, 0, 0, 0, 1>(7),
         make_entry<512, kStrided, StC128, 16, kC128, 16, 16, 0, 0, 0, 1>(8),
         XCAND(400), XCAND(480), XCAND(576), XCAND(640), XCAND(720), XCAND(768), XCAND(960),
+        make_real_entry<256, StC128, 16, kC128, 1>(),
     };
 }
 

@@ -71,6 +71,7 @@ std::vector<Entry> entries_c64() {
         make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 0, 0, 1>(6),
         make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 1, 0, 1>(7),
         XCAND(400), XCAND(480), XCAND(576), XCAND(640), XCAND(720), XCAND(768), XCAND(960),
+        make_real_entry<256, StC64, 8, kC64, 1>(), make_real_entry<512, StC64, 8, kC64, 1>(),
     };
 }
 
