@@ -20,7 +20,8 @@ namespace dev {
 // the stores only; 17 and 18 are 6 and 16 copying the first half of the next tile into LDS
 // during the current one (whole tiles, persistent grids); 19 and 20 are 16 and 6 loading
 // the next tile into registers during the current one (persistent grids); 21 and 22
-// are 8 and 9 with the copy of 17 (256-thread blocks, two per CU);
+// are 8 and 9 with the copy of 17 (256-thread blocks, two per CU); 23 and 24 are 20 with
+// the non-temporal hint on the loads and on the loads and stores;
 // at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order, 10 and 11 are 6 and 7 with that
 // copy; contiguous 3: non-temporal
 #define CAND(N, EW, LW, EW2, LW2)                                                \
@@ -62,6 +63,8 @@ std::vector<Entry> entries_c16b() {
         make_lanes_entry<512, StHalf<true>, kC16B, 0, 512, false, false, false, true>(20),
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 0, 256, false, false, true>(21), 8),
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 3, 256, false, false, true>(22), 8),
+        with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 1, 512, false, false, false, true>(23), 20),
+        with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 3, 512, false, false, false, true>(24), 20),
         make_lanes_entry<1024, StHalf<true>, kC16B, 0>(6), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3>(7), 6),
         make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3, 512, true>(9), 8),
         with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, false, false, true>(10), 6),
