@@ -19,7 +19,8 @@ namespace dev {
 // 12 and 13 (length 512) 8 with the non-temporal hint on the loads only and on the
 // stores only, 14 is 12 in the XCD-contiguous order, 15 and 16 are 12 and 8 with the
 // tiles in reverse order, 17 and 18 are 8 and 9 copying the first half of the next tile into LDS
-// during the current one (whole tiles, persistent grids); at 1024, 8 and 9 are 6 and 7 with the
+// during the current one (whole tiles, persistent grids), 19 and 20 are 17 with the
+// non-temporal hint on the loads only and on the stores only; at 1024, 8 and 9 are 6 and 7 with the
 // XCD-contiguous order, 10 to 12 are 6 with that copy (non-temporal stores in 11, loads and stores
 // in 12); contiguous 3:
 // non-temporal;
@@ -67,6 +68,8 @@ std::vector<Entry> entries_c64() {
         with_plain(make_lanes_entry<1024, StC64, kC64, 3, 512, false, false, true>(12), 6),
         with_plain(make_lanes_entry<512, StC64, kC64, 0, 256, false, false, true>(17), 8),
         with_plain(make_lanes_entry<512, StC64, kC64, 3, 256, false, false, true>(18), 8),
+        with_plain(make_lanes_entry<512, StC64, kC64, 1, 256, false, false, true>(19), 8),
+        with_plain(make_lanes_entry<512, StC64, kC64, 2, 256, false, false, true>(20), 8),
         CAND(384, 16, 32, 32, 32),
         make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 0, 0, 1>(6),
         make_entry<384, kStrided, StC64, 8, kC64, 0, 0, 0, 1, 0, 1>(7),

@@ -23,8 +23,8 @@ FWD, BWD = croft.CROFT_FORWARD, croft.CROFT_BACKWARD
 
 # (dtype, (nz, ny, nx), axis of the pass, length, candidates with the copy)
 CASES = [
-    (C64, (512, 256, 128), 2, 512, (17, 18)),
-    (C64, (256, 512, 128), 1, 512, (17, 18)),
+    (C64, (512, 256, 128), 2, 512, (17, 18, 19, 20)),
+    (C64, (256, 512, 128), 1, 512, (17, 18, 19, 20)),
     (C64, (1024, 64, 256), 2, 1024, (10, 11, 12)),
     (F16, (512, 128, 256), 2, 512, (17, 18, 21, 22)),
     (BF16, (512, 128, 256), 2, 512, (17, 18, 21, 22)),
