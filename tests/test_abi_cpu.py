@@ -331,7 +331,7 @@ def test_builtin_one_line_per_lane_at_1024(tmp_path, monkeypatch):
 
 
 def test_wisdom_unknown_candidate_falls_back_to_default(tmp_path, monkeypatch):
-    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 19 1\n", 512, 512, 512)
+    passes = _describe_with_wisdom(tmp_path, monkeypatch, "512 1 0 99 1\n", 512, 512, 512)
     assert passes[1]["candidate"] == "0"
 
 
