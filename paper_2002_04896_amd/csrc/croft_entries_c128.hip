@@ -15,7 +15,8 @@ namespace dev {
 // 4 wide tile with fewer threads (EW2 elements per thread, LW2 lines),
 // 5 wide tile with non-temporal loads and stores; contiguous 3: non-temporal;
 // fused multiply pass: 0 default shape, 1 wide tile (EW, LW); strided 512: 6, 7, 8 are 1, 2, 4
-// with each XCD taking a contiguous run of tiles
+// with each XCD taking a contiguous run of tiles, 9 and 10 are 4 and 8 with non-temporal loads
+// and stores
 #define CAND(N, EW, LW, EW2, LW2)                                                \
     make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 1, 1>(1),                 \
         make_entry<N, kContiguous, StC128, 16, kC128, 0, 0, 0, 0>(2),             \
@@ -47,6 +48,8 @@ std::vector<Entry> entries_c128() {
         make_entry<512, kStrided, StC128, 16, kC128, 0, 0, 0, 0, 0, 1>(6),
         make_entry<512, kStrided, StC128, 16, kC128, 8, 16, 0, 0, 0, 1>(7),
         make_entry<512, kStrided, StC128, 16, kC128, 16, 16, 0, 0, 0, 1>(8),
+        make_entry<512, kStrided, StC128, 16, kC128, 16, 16, 0, 0, 1>(9),
+        make_entry<512, kStrided, StC128, 16, kC128, 16, 16, 0, 0, 1, 1>(10),
         XCAND(400), XCAND(480), XCAND(576), XCAND(640), XCAND(720), XCAND(768), XCAND(960),
         make_real_entry<256, StC128, 16, kC128, 1>(),
     };
