@@ -21,7 +21,8 @@ namespace dev {
 // during the current one (whole tiles, persistent grids); 19 and 20 are 16 and 6 loading
 // the next tile into registers during the current one (persistent grids); 21 and 22
 // are 8 and 9 with the copy of 17 (256-thread blocks, two per CU); 23 and 24 are 20 with
-// the non-temporal hint on the loads and on the loads and stores;
+// the non-temporal hint on the loads and on the loads and stores; 25 and 26 are 12 and 8
+// with the tiles in reverse order;
 // at 1024, 8 and 9 are 6 and 7 with the XCD-contiguous order, 10 and 11 are 6 and 7 with that
 // copy; contiguous 3: non-temporal
 #define CAND(N, EW, LW, EW2, LW2)                                                \
@@ -65,6 +66,8 @@ std::vector<Entry> entries_c16b() {
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 3, 256, false, false, true>(22), 8),
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 1, 512, false, false, false, true>(23), 20),
         with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 3, 512, false, false, false, true>(24), 20),
+        with_plain(make_lanes_entry<512, StHalf<true>, kC16B, 1, 256, false, true>(25), 26),
+        make_lanes_entry<512, StHalf<true>, kC16B, 0, 256, false, true>(26),
         make_lanes_entry<1024, StHalf<true>, kC16B, 0>(6), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3>(7), 6),
         make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, true>(8), with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 3, 512, true>(9), 8),
         with_plain(make_lanes_entry<1024, StHalf<true>, kC16B, 0, 512, false, false, true>(10), 6),

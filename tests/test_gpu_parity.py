@@ -284,7 +284,7 @@ def test_every_compiled_candidate_gives_identical_bits(dtype, shape, direction, 
     lengths = {(p["n"], p["kind"]) for p in info["passes"]}
     tried = 0
     for n, kind in lengths:
-        for cand in range(25):
+        for cand in range(27):
             for waves in (0, 1, 3):
                 wisdom.write_text(f"{n} {kind} {dtype} {cand} {waves}\n")
                 got, got_e, ginfo = run()
